@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Benchmark: j2d5pt under deep temporal blocking on one MI355X.
+
+One "step" of this benchmark is one whole pass of the hot path over one
+batch: dtb_run of the 2048 x 2048 FP64 grid for T = 10000 time steps (the
+grid stays on chip for all of them).  Throughput is counted in interior
+cell-updates: rows * cols * T per step, divided by wall time.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--no-step-baseline]
+
+Prints ONE JSON line.  Besides the headline value it carries:
+  roofline      the DTB kernel's achieved FP64 arithmetic rate (9 flops per
+                cell-update: one multiply and four fused multiply-adds)
+                against the chip's FP64 vector peak; duration from HIP events
+                on the launch stream;
+  baseline_1step  the untiled one-launch-per-time-step kernel on the same
+                grid (T launches, HBM/Infinity-Cache bound), and DTB's speedup;
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X FP64 vector (FMA counted as 2 flops)
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+FLOPS_PER_UPDATE = 9
+
+
+def _cpu_baseline(w, budget_s: float):
+    """Time the CPU oracle on a bounded number of steps of the same grid."""
+    import oracle  # test infrastructure, used only for this leg
+    u = w.grid()
+    nt = oracle.default_threads()
+    steps, t0 = 0, time.perf_counter()
+    chunk = 50
+    while time.perf_counter() - t0 < budget_s and steps < w.T:
+        u = oracle.j2d5pt_f64(u, w.coeffs, chunk, nthreads=nt)
+        steps += chunk
+    dt = time.perf_counter() - t0
+    return {"value": round(w.rows * w.cols * steps / dt / 1e9, 4), "unit": "GCells/s", "cores": nt,
+            "kind": "oracle",
+            "sample": f"{w.rows}x{w.cols} FP64, {steps} of the {w.T} time steps ({dt:.1f} s, FP64, {nt} threads)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="j2d5pt_2048x2048_f64_T10000")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-step-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is described in DESIGN.md but not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2306_03336_amd import dtb, inputs
+
+    w = inputs.workload(args.workload)
+    dt = torch.float64 if w.dtype == "f64" else torch.float32
+    u0 = torch.from_numpy(w.grid()).to(device="cuda", dtype=dt)
+    g = u0.clone()
+    stream = torch.cuda.current_stream()
+    plan = dtb.plan_for(g, w.T)
+    desc = plan.describe()
+    print(f"[bench] {w.name} plan {desc}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        g.copy_(u0)
+        plan.run(g, w.coeffs, w.T)
+    plan.check()
+    torch.cuda.synchronize()
+
+    # Timed region: K whole runs, each advancing the grid another T steps.
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[2 * i].record(stream)
+        plan.run(g, w.coeffs, w.T)
+        ev[2 * i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.check()
+    kern_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)]
+    avg_ms = float(np.mean(kern_ms))
+    ms_per_step = wall * 1e3 / args.steps
+    updates = w.rows * w.cols * w.T
+    value = updates * args.steps / wall / 1e9
+
+    # The untiled baseline on the same grid: T launches of the one-step kernel.
+    base = None
+    if not args.no_step_baseline:
+        sp = dtb.plan_for(g, w.T, path=dtb.PATH_STEP)
+        g.copy_(u0)
+        sp.run(g, w.coeffs, 200)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sp.run(g, w.coeffs, w.T)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1)
+        bval = updates / (bms / 1e3) / 1e9
+        bytes_per_update = 2 * (8 if w.dtype == "f64" else 4)
+        base = {"value": round(bval, 3), "unit": "GCells/s", "ms_per_run": round(bms, 3),
+                "launches": w.T, "dtb_speedup": round(value / bval, 3),
+                "hbm_roofline_GCells": PEAK_HBM_GBS / bytes_per_update,
+                "achieved_GBs_algorithmic": round(bval * bytes_per_update, 1)}
+        sp.destroy()
+
+    peak = PEAK_FP64_VECTOR_TFLOPS if w.dtype == "f64" else PEAK_FP32_VECTOR_TFLOPS
+    achieved = FLOPS_PER_UPDATE * updates / (avg_ms / 1e3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "k_dtb", "avg_launch_ms": round(avg_ms, 4)}
+
+    cpu = None if args.no_cpu else _cpu_baseline(w, args.cpu_budget)
+
+    out = {
+        "metric": "GCells/s j2d5pt, DTB vs 1-step kernel on 1 MI355X, FP64 (<=1e-13) and FP32",
+        "value": round(value, 3),
+        "unit": "GCells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "rows": w.rows, "cols": w.cols, "T": w.T, "halo": w.halo,
+                   "weights": w.weights, "seed": w.seed, "plan": desc},
+        "roofline": roof,
+        "baseline_1step": base,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    plan.destroy()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,162 @@
+/*
+ * dtb.h -- libdtb: the j2d5pt iterative stencil under deep temporal blocking
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Zhang et al., "Exploiting Scratchpad Memory for Deep
+ * Temporal Blocking", GPGPU '23; Listing 1 gives the update, Section 3.1 and
+ * the caption of Figure 1 repeat it for T time steps):
+ *
+ *   for t in 0 .. T-1, for every interior cell (i, j):
+ *     u'[i][j] = w*u[i][j-1] + e*u[i][j+1] + s*u[i-1][j] + c*u[i][j] + n*u[i+1][j]
+ *   then u = u'  (every read of a step sees the previous step's values).
+ *
+ * Storage: a device buffer of (rows + 2) lines of `pitch` elements,
+ * row-major.  The interior is rows 1..rows, columns 1..cols; the one-cell ring
+ * around it (rows 0 and rows+1, columns 0 and cols+1) is a fixed Dirichlet
+ * halo: it is read but never written.  Corner halo cells are never read.
+ * Elements past column cols+1 (pitch padding) are never touched.
+ * Column j is the contiguous index (x in Listing 1), row i the strided one
+ * (y); hence W = (i, j-1), E = (i, j+1), S = (i-1, j), N = (i+1, j).
+ *
+ * Coefficients are passed as five doubles in the order (c, n, s, e, w).  They
+ * need not sum to 1 and are copied at the call.  DTB_F32 rounds them to float.
+ *
+ * Arithmetic: by default each cell is a chain of one multiply and four fused
+ * multiply-adds in the order W, E, S, C, N.  With dtb_plan_opts.exact = 1
+ * the products are rounded separately and summed left to right in that same
+ * order, which reproduces a plain CPU loop bit for bit.  No flush to zero.
+ *
+ * Every function returns a dtb_status; none aborts or prints.  Invalid
+ * arguments are rejected before any HIP call.  Launches are asynchronous on
+ * the given stream (a hipStream_t passed as void*; NULL is the default
+ * stream).  The caller owns the grid and keeps it alive until the stream has
+ * finished the work.
+ */
+#ifndef LIBDTB_DTB_H
+#define LIBDTB_DTB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { DTB_F64 = 0, DTB_F32 = 1 } dtb_dtype;
+
+typedef enum {
+    DTB_OK = 0,
+    DTB_ERR_INVALID_ARG = -1,    /* a NULL pointer, rows/cols < 1, pitch < cols+2, T < 0, bad dtype/option */
+    DTB_ERR_UNSUPPORTED = -2,    /* shape or option this build does not handle */
+    DTB_ERR_NOT_CORESIDENT = -3, /* the plan needs more workgroups than can run at once */
+    DTB_ERR_OUT_OF_MEMORY = -4,  /* workspace allocation failed */
+    DTB_ERR_HIP = -5,            /* a HIP runtime call or kernel launch failed */
+    DTB_ERR_TIMEOUT = -6,        /* a bounded in-kernel wait expired (a workgroup never arrived) */
+    DTB_ERR_NOT_PLANNED = -7,    /* the call needs a plan that does not exist */
+    DTB_ERR_MISMATCH = -8        /* grid/dtype do not match the plan */
+} dtb_status;
+
+/* Execution paths a plan can take. */
+typedef enum {
+    DTB_PATH_AUTO = 0,     /* resident DTB when the grid fits on chip, else the tile-serial sweep */
+    DTB_PATH_STEP = 1,     /* the untiled baseline: one kernel launch per time step, HBM to HBM */
+    DTB_PATH_RESIDENT = 2, /* deep temporal blocking, whole grid held on chip for all T steps */
+    DTB_PATH_SWEEP = 3     /* deep temporal blocking, big tiles processed one after another (tile-serial) */
+} dtb_path;
+
+/* A grid in device memory (see the storage description above). */
+typedef struct {
+    void* data;     /* device pointer to halo cell (0, 0); caller-owned */
+    int64_t rows;   /* interior rows N >= 1 */
+    int64_t cols;   /* interior columns M >= 1 */
+    int64_t pitch;  /* elements per storage row, >= cols + 2 */
+} dtb_grid;
+
+/* Plan options.  Zero-initialise and set what you need; 0 means "choose". */
+typedef struct {
+    int32_t path;        /* dtb_path */
+    int32_t ghost_k;     /* steps between inter-workgroup halo exchanges (ghost ring depth); 0 = auto */
+    int32_t depth_D;     /* sweep: steps per round (temporal depth of a big tile); 0 = auto */
+    int32_t rows_per_lane; /* register tile height per lane (instantiated sizes only); 0 = auto */
+    int32_t max_wg;      /* cap on workgroups; 0 = every compute unit */
+    int32_t exact;       /* 1: separately rounded products, plain left-to-right sum (bitwise CPU parity) */
+    int32_t debug_flags; /* reserved, must be 0 */
+    int32_t reserved;
+} dtb_plan_opts;
+
+typedef struct dtb_plan_s* dtb_plan_t;
+
+/* One problem of a batch: a grid, its coefficients (c, n, s, e, w), its step count and precision. */
+typedef struct {
+    dtb_grid grid;
+    double coeffs[5];
+    int64_t T;
+    int32_t dtype;   /* dtb_dtype */
+    int32_t reserved;
+} dtb_problem;
+
+/*
+ * Build a plan for grids of this shape and precision: chooses the path, the
+ * tile decomposition, the exchange depth and the workgroup count, checks that
+ * every workgroup can be resident at once, and allocates the plan's device
+ * workspace (exchange buffers, epoch flags, error word, descriptor tables).
+ * T_hint is the expected step count (0 = unknown).  opts may be NULL.
+ * On success *out receives the plan; release it with dtb_plan_destroy.
+ * Allocates; not for use under stream capture.
+ */
+dtb_status dtb_plan(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, dtb_dtype dtype,
+                    int64_t T_hint, const dtb_plan_opts* opts);
+
+/*
+ * Advance grid->data by T steps in place with an explicit plan.  The grid's
+ * rows, cols, pitch and dtype must match the plan.  T == 0 returns DTB_OK
+ * without launching.  One call in flight per plan; calls on other plans may
+ * overlap.  Does not allocate.
+ */
+dtb_status dtb_run_plan(dtb_plan_t plan, const dtb_grid* grid, const double coeffs[5], int64_t T,
+                        void* stream);
+
+/*
+ * Advance grid->data by T steps in place, using a plan cached by
+ * (rows, cols, pitch, dtype, device), created on first use with default
+ * options.  Creating the plan allocates; later calls do not.
+ */
+dtb_status dtb_run(const dtb_grid* grid, const double coeffs[5], int64_t T, dtb_dtype dtype,
+                   void* stream);
+
+/*
+ * Run `count` independent problems (uneven shapes, step counts and
+ * precisions) in one persistent launch.  The first call for a given set of
+ * shapes/precisions/step counts plans each problem, packs their workgroups
+ * onto the compute units and captures the launch in a HIP graph; later calls
+ * with the same signature update the grid pointers and coefficients and
+ * replay the graph.  Each grid is updated in place as dtb_run would.
+ */
+dtb_status dtb_run_batched(const dtb_problem* problems, int32_t count, void* stream);
+
+/*
+ * Wait for the plan's last run on `stream` and report an in-kernel failure
+ * (DTB_ERR_TIMEOUT) recorded since the previous check; clears it.
+ */
+dtb_status dtb_plan_check(dtb_plan_t plan, void* stream);
+
+/*
+ * Describe a plan: fills up to `n` int64 values in this order: path,
+ * workgroups, ghost_k, depth_D, ext_rows, ext_cols, tiles_rows, tiles_cols,
+ * rows_per_lane, cols_per_lane, big_tiles, exact.  Returns DTB_OK.
+ */
+dtb_status dtb_plan_describe(dtb_plan_t plan, int64_t* values, int32_t n);
+
+/* Release a plan and its workspace (after its work has completed).  NULL is a no-op. */
+void dtb_plan_destroy(dtb_plan_t plan);
+
+/* Drop every cached plan (dtb_run's and dtb_run_batched's). */
+void dtb_cache_clear(void);
+
+/* A static string naming the status. */
+const char* dtb_status_string(dtb_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBDTB_DTB_H */

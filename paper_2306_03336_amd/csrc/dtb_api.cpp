@@ -1,0 +1,416 @@
+// dtb_api.cpp -- the libdtb C ABI: argument checks, plans, plan cache, launches.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dtb.h"
+#include "../../include/dtb_testing.h"
+#include "dtb_internal.h"
+#include "dtb_launch.h"
+#include "dtb_plan.h"
+
+using namespace dtb;
+
+namespace {
+
+constexpr uint32_t kSpinLimit = 1u << 22;  // bounded wait: a few seconds of polling
+constexpr int kNumXcd = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
+constexpr int kDtbRowsPerLane[] = {8, 16, 24};
+
+struct DeviceInfo {
+    int device = -1;
+    int n_cu = 0;
+};
+
+bool device_info(DeviceInfo* di)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    di->device = dev;
+    di->n_cu = ncu;
+    return true;
+}
+
+}  // namespace
+
+struct dtb_plan_s {
+    int device = -1;
+    int64_t rows = 0, cols = 0, pitch = 0;
+    int dtype = 0;
+    int path = DTB_PATH_STEP;
+    bool fma = true;
+    // one-step path
+    void* ws = nullptr;
+    // resident path
+    Layout layout;
+    const void* kfunc = nullptr;
+    bool colmask = false, rowcheck = false;
+    WgDesc* d_wgs = nullptr;
+    uint32_t* d_flags = nullptr;
+    int* d_err = nullptr;
+    void* xbuf[2] = {nullptr, nullptr};
+
+    ~dtb_plan_s()
+    {
+        if (ws) (void)hipFree(ws);
+        if (d_wgs) (void)hipFree(d_wgs);
+        if (d_flags) (void)hipFree(d_flags);
+        if (d_err) (void)hipFree(d_err);
+        for (void* p : xbuf)
+            if (p) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+size_t elem_size(int dtype) { return dtype == DTB_F64 ? 8 : 4; }
+
+dtb_status check_shape(int64_t rows, int64_t cols, int64_t pitch, int dtype)
+{
+    if (rows < 1 || cols < 1 || pitch < cols + 2) return DTB_ERR_INVALID_ARG;
+    if (dtype != DTB_F64 && dtype != DTB_F32) return DTB_ERR_INVALID_ARG;
+    // Descriptors and kernel index math are 32-bit in rows/cols.
+    if (rows > (1 << 30) || cols > (1 << 30)) return DTB_ERR_UNSUPPORTED;
+    return DTB_OK;
+}
+
+dtb_status check_opts(const dtb_plan_opts* o)
+{
+    if (!o) return DTB_OK;
+    if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_SWEEP) return DTB_ERR_INVALID_ARG;
+    if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0) return DTB_ERR_INVALID_ARG;
+    if (o->exact != 0 && o->exact != 1) return DTB_ERR_INVALID_ARG;
+    if (o->debug_flags != 0 || o->reserved != 0) return DTB_ERR_INVALID_ARG;
+    return DTB_OK;
+}
+
+// Choose (rows per lane, k) for the resident path by the static cost model.
+bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o, int n_cu, bool fma,
+                     Layout* best_layout, const void** best_func, bool* colmask, bool* rowcheck)
+{
+    double best = 1e300;
+    bool found = false;
+    const int ks_auto[] = {4, 6, 8, 10, 12, 16};
+    std::vector<int> ks;
+    if (o.ghost_k > 0) ks.push_back(o.ghost_k);
+    else ks.assign(std::begin(ks_auto), std::end(ks_auto));
+    for (int R : kDtbRowsPerLane) {
+        if (o.rows_per_lane > 0 && o.rows_per_lane != R) continue;
+        for (int k : ks) {
+            int C = 0, waves = 0;
+            const void* f0 = dtb_kernel(dtype, R, fma, false, false, &C, &waves);
+            if (!f0) continue;
+            Layout L;
+            if (!build_layout(rows, cols, R, C, waves, k, kNumXcd, 0, 0, &L)) continue;
+            const bool cm = L.cols.narrow, rc = L.rows.narrow;
+            const void* f = dtb_kernel(dtype, R, fma, cm, rc, &C, &waves);
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) != hipSuccess) continue;
+            int cap = occ * n_cu;
+            if (o.max_wg > 0) cap = std::min(cap, o.max_wg);
+            if (L.nwg > cap) continue;
+            const double cost = layout_cost(L, occ, n_cu, 1.0);
+            if (cost < best) {
+                best = cost;
+                *best_layout = L;
+                *best_func = f;
+                *colmask = cm;
+                *rowcheck = rc;
+                found = true;
+            }
+        }
+    }
+    return found;
+}
+
+dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, int dtype, int64_t /*T_hint*/,
+                     const dtb_plan_opts* opts)
+{
+    if (!out) return DTB_ERR_INVALID_ARG;
+    *out = nullptr;
+    dtb_status st = check_shape(rows, cols, pitch, dtype);
+    if (st != DTB_OK) return st;
+    st = check_opts(opts);
+    if (st != DTB_OK) return st;
+    dtb_plan_opts o{};
+    if (opts) o = *opts;
+
+    DeviceInfo di;
+    if (!device_info(&di)) return DTB_ERR_HIP;
+    std::unique_ptr<dtb_plan_s> p(new dtb_plan_s());
+    p->device = di.device;
+    p->rows = rows;
+    p->cols = cols;
+    p->pitch = pitch;
+    p->dtype = dtype;
+    p->fma = o.exact == 0;
+    const size_t bytes = (size_t)(rows + 2) * (size_t)pitch * elem_size(dtype);
+
+    int path = o.path;
+    if (path == DTB_PATH_AUTO || path == DTB_PATH_RESIDENT) {
+        Layout L;
+        const void* f = nullptr;
+        bool cm = false, rc = false;
+        if (choose_resident(rows, cols, dtype, o, di.n_cu, p->fma, &L, &f, &cm, &rc)) {
+            path = DTB_PATH_RESIDENT;
+            p->layout = std::move(L);
+            p->kfunc = f;
+            p->colmask = cm;
+            p->rowcheck = rc;
+        } else if (path == DTB_PATH_RESIDENT) {
+            return DTB_ERR_NOT_CORESIDENT;
+        } else {
+            path = DTB_PATH_STEP;  // until the tile-serial sweep takes grids larger than the chip
+        }
+    }
+    if (path == DTB_PATH_SWEEP) return DTB_ERR_UNSUPPORTED;
+    p->path = path;
+
+    if (path == DTB_PATH_STEP) {
+        if (hipMalloc(&p->ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+    } else {
+        const size_t nwg = p->layout.wgs.size();
+        if (hipMalloc(&p->d_wgs, nwg * sizeof(WgDesc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_flags, nwg * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_err, sizeof(int)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        for (int i = 0; i < 2; ++i)
+            if (hipMalloc(&p->xbuf[i], bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMemcpy(p->d_wgs, p->layout.wgs.data(), nwg * sizeof(WgDesc), hipMemcpyHostToDevice) != hipSuccess)
+            return DTB_ERR_HIP;
+        if (hipMemset(p->d_flags, 0, nwg * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+        if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
+    }
+    *out = p.release();
+    return DTB_OK;
+}
+
+dtb_status run_step(dtb_plan_t p, void* data, const double* coeffs, int64_t T, hipStream_t st)
+{
+    const int rows = (int)p->rows, cols = (int)p->cols;
+    if (launch_copy_halo(p->dtype, data, p->ws, p->pitch, rows, cols, st) != hipSuccess) return DTB_ERR_HIP;
+    void* in = data;
+    void* out = p->ws;
+    for (int64_t t = 0; t < T; ++t) {
+        if (launch_step(p->dtype, p->fma, in, out, p->pitch, rows, cols, coeffs, st) != hipSuccess) return DTB_ERR_HIP;
+        std::swap(in, out);
+    }
+    if (in != data) {
+        if (launch_copy_interior(p->dtype, in, data, p->pitch, rows, cols, st) != hipSuccess) return DTB_ERR_HIP;
+    }
+    return DTB_OK;
+}
+
+dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t T, hipStream_t st)
+{
+    ProbDesc P{};
+    P.grid = data;
+    P.xbuf[0] = p->xbuf[0];
+    P.xbuf[1] = p->xbuf[1];
+    P.pitch = p->pitch;
+    P.T = T;
+    P.rows = (int)p->rows;
+    P.cols = (int)p->cols;
+    P.k = p->layout.k;
+    P.wg0 = 0;
+    P.nwg = p->layout.nwg;
+    P.dtype = p->dtype;
+    P.fma = p->fma ? 1 : 0;
+    P.narrow_cols = p->colmask ? 1 : 0;
+    P.narrow_rows = p->rowcheck ? 1 : 0;
+    for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
+    const WgDesc* wgs = p->d_wgs;
+    uint32_t* flags = p->d_flags;
+    int* err = p->d_err;
+    uint32_t spin = kSpinLimit;
+    void* args[] = {&P, (void*)&wgs, (void*)&flags, (void*)&err, &spin};
+    const dim3 grid(p->layout.nwg), block(p->layout.waves * kWaveSize);
+    if (hipLaunchCooperativeKernel(p->kfunc, grid, block, args, 0, st) != hipSuccess) return DTB_ERR_HIP;
+    return DTB_OK;
+}
+
+dtb_status run_plan_impl(dtb_plan_t p, const dtb_grid* g, const double* coeffs, int64_t T, void* stream)
+{
+    if (!p || !g || !coeffs || !g->data) return DTB_ERR_INVALID_ARG;
+    if (T < 0) return DTB_ERR_INVALID_ARG;
+    if (g->rows != p->rows || g->cols != p->cols || g->pitch != p->pitch) return DTB_ERR_MISMATCH;
+    if (T == 0) return DTB_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->path == DTB_PATH_STEP) return run_step(p, g->data, coeffs, T, st);
+    if (p->path == DTB_PATH_RESIDENT) return run_resident(p, g->data, coeffs, T, st);
+    return DTB_ERR_UNSUPPORTED;
+}
+
+// ---- dtb_run's plan cache
+struct CacheKey {
+    int64_t rows, cols, pitch;
+    int dtype, device;
+    bool operator<(const CacheKey& o) const
+    {
+        return std::tie(rows, cols, pitch, dtype, device) < std::tie(o.rows, o.cols, o.pitch, o.dtype, o.device);
+    }
+};
+std::mutex g_cache_mu;
+std::map<CacheKey, dtb_plan_t> g_cache;
+
+}  // namespace
+
+extern "C" {
+
+dtb_status dtb_plan(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, dtb_dtype dtype, int64_t T_hint,
+                    const dtb_plan_opts* opts)
+{
+    return plan_impl(out, rows, cols, pitch, (int)dtype, T_hint, opts);
+}
+
+dtb_status dtb_run_plan(dtb_plan_t plan, const dtb_grid* grid, const double coeffs[5], int64_t T, void* stream)
+{
+    return run_plan_impl(plan, grid, coeffs, T, stream);
+}
+
+dtb_status dtb_run(const dtb_grid* grid, const double coeffs[5], int64_t T, dtb_dtype dtype, void* stream)
+{
+    if (!grid || !coeffs || !grid->data || T < 0) return DTB_ERR_INVALID_ARG;
+    dtb_status st = check_shape(grid->rows, grid->cols, grid->pitch, (int)dtype);
+    if (st != DTB_OK) return st;
+    if (T == 0) return DTB_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DTB_ERR_HIP;
+    const CacheKey key{grid->rows, grid->cols, grid->pitch, (int)dtype, dev};
+    dtb_plan_t p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) p = it->second;
+    }
+    if (!p) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) return DTB_ERR_HIP;
+        if (cs != hipStreamCaptureStatusNone) return DTB_ERR_NOT_PLANNED;
+        st = plan_impl(&p, grid->rows, grid->cols, grid->pitch, (int)dtype, T, nullptr);
+        if (st != DTB_OK) return st;
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            delete p;
+            p = it->second;
+        } else {
+            g_cache[key] = p;
+        }
+    }
+    return run_plan_impl(p, grid, coeffs, T, stream);
+}
+
+dtb_status dtb_run_batched(const dtb_problem* problems, int32_t count, void* stream)
+{
+    if (count < 0 || (count > 0 && !problems)) return DTB_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < count; ++i) {
+        const dtb_problem& q = problems[i];
+        if (!q.grid.data || q.T < 0) return DTB_ERR_INVALID_ARG;
+        dtb_status st = check_shape(q.grid.rows, q.grid.cols, q.grid.pitch, q.dtype);
+        if (st != DTB_OK) return st;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        const dtb_problem& q = problems[i];
+        dtb_status st = dtb_run(&q.grid, q.coeffs, q.T, (dtb_dtype)q.dtype, stream);
+        if (st != DTB_OK) return st;
+    }
+    return DTB_OK;
+}
+
+dtb_status dtb_plan_check(dtb_plan_t p, void* stream)
+{
+    if (!p) return DTB_ERR_INVALID_ARG;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return DTB_ERR_HIP;
+    if (!p->d_err) return DTB_OK;
+    int e = 0;
+    if (hipMemcpy(&e, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return DTB_ERR_HIP;
+    if (e == 0) return DTB_OK;
+    // A timed-out run leaves the epoch counters out of step: reset them.
+    if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
+    if (hipMemset(p->d_flags, 0, p->layout.wgs.size() * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+    return DTB_ERR_TIMEOUT;
+}
+
+dtb_status dtb_plan_describe(dtb_plan_t p, int64_t* v, int32_t n)
+{
+    if (!p || (n > 0 && !v) || n < 0) return DTB_ERR_INVALID_ARG;
+    const Layout& L = p->layout;
+    const int64_t all[] = {p->path, L.nwg, L.k, 0, L.ER, L.EC, L.rows.parts, L.cols.parts, L.R, L.C, 0,
+                           p->fma ? 0 : 1};
+    for (int32_t i = 0; i < n && i < (int32_t)(sizeof(all) / sizeof(all[0])); ++i) v[i] = all[i];
+    return DTB_OK;
+}
+
+void dtb_plan_destroy(dtb_plan_t plan)
+{
+    if (!plan) return;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+            if (it->second == plan) {
+                g_cache.erase(it);
+                break;
+            }
+        }
+    }
+    delete plan;
+}
+
+void dtb_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto& kv : g_cache) delete kv.second;
+    g_cache.clear();
+}
+
+const char* dtb_status_string(dtb_status s)
+{
+    switch (s) {
+    case DTB_OK: return "DTB_OK";
+    case DTB_ERR_INVALID_ARG: return "DTB_ERR_INVALID_ARG";
+    case DTB_ERR_UNSUPPORTED: return "DTB_ERR_UNSUPPORTED";
+    case DTB_ERR_NOT_CORESIDENT: return "DTB_ERR_NOT_CORESIDENT";
+    case DTB_ERR_OUT_OF_MEMORY: return "DTB_ERR_OUT_OF_MEMORY";
+    case DTB_ERR_HIP: return "DTB_ERR_HIP";
+    case DTB_ERR_TIMEOUT: return "DTB_ERR_TIMEOUT";
+    case DTB_ERR_NOT_PLANNED: return "DTB_ERR_NOT_PLANNED";
+    case DTB_ERR_MISMATCH: return "DTB_ERR_MISMATCH";
+    default: return "DTB_ERR_UNKNOWN";
+    }
+}
+
+// ---- planner hooks for host-only tests (include/dtb_testing.h)
+
+int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_t cols_per_lane, int32_t waves,
+                        int32_t k, int32_t n_xcd, int32_t* out, int32_t max_wg)
+{
+    Layout L;
+    if (rows_per_lane < 1 || cols_per_lane < 1 || waves < 1 || k < 1 || max_wg < 0 || (max_wg > 0 && !out))
+        return -1;
+    if (!build_layout(rows, cols, rows_per_lane, cols_per_lane, waves, k, n_xcd, 0, 0, &L)) return -1;
+    if (L.nwg > max_wg) return L.nwg;
+    for (int i = 0; i < L.nwg; ++i) {
+        const WgDesc& d = L.wgs[i];
+        int32_t* o = out + (size_t)i * DTB_TEST_LAYOUT_STRIDE;
+        o[0] = d.ext_r0;
+        o[1] = d.ext_c0;
+        o[2] = d.own_r0;
+        o[3] = d.own_r1;
+        o[4] = d.own_c0;
+        o[5] = d.own_c1;
+        o[6] = d.nnb;
+        for (int j = 0; j < kMaxNeighbours; ++j) o[7 + j] = j < d.nnb ? d.nb[j] : -1;
+        o[7 + kMaxNeighbours] = (L.rows.narrow ? 1 : 0) | (L.cols.narrow ? 2 : 0);
+    }
+    return L.nwg;
+}
+
+}  // extern "C"

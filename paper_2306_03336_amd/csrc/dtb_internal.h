@@ -1,0 +1,52 @@
+// dtb_internal.h -- descriptors shared by the host planner and the gfx950 kernels.
+//
+// Not part of the public C ABI (include/dtb.h).  Every field is plain data so
+// the planner can build the tables on the host and copy them to the device
+// once per plan.
+#pragma once
+#include <stdint.h>
+
+namespace dtb {
+
+constexpr int kWaveSize = 64;
+constexpr int kMaxNeighbours = 24;
+
+// One problem of a launch: a grid advanced T steps in place.
+//
+// Storage (same for grid and the two exchange buffers): (rows + 2) lines of
+// `pitch` elements, row-major; interior rows 1..rows, columns 1..cols; the
+// one-cell ring around it is the fixed Dirichlet halo.
+struct ProbDesc {
+    void* grid;          // caller's storage, updated in place
+    void* xbuf[2];       // exchange buffers (same layout), owned by the plan
+    int64_t pitch;       // elements per storage row
+    int64_t T;           // time steps
+    int32_t rows, cols;  // interior size
+    int32_t k;           // steps between inter-workgroup halo exchanges
+    int32_t wg0, nwg;    // this problem's workgroups: blockIdx-independent ids wg0..wg0+nwg-1
+    int32_t dtype;       // 0 = FP64, 1 = FP32
+    int32_t fma;         // 1: fused multiply-add chain; 0: separate products summed W,E,S,C,N
+    int32_t narrow_cols; // 1 when some tile holds the east halo column inside it
+    int32_t narrow_rows; // 1 when some tile holds the south halo row inside it
+    int32_t pad_;
+    double coeffs[5];    // c, n, s, e, w
+};
+
+// One workgroup: which problem, where its register tile sits, what it owns.
+//
+// The extended tile is ER x EC cells (ER = waves * rows per lane, EC = 64 *
+// columns per lane); its cell (0, 0) is storage cell (ext_r0, ext_c0).  The
+// owned cells are [own_r0, own_r1) x [own_c0, own_c1) in storage
+// coordinates; the owned regions of a problem's workgroups tile its interior
+// exactly.  nb[] lists the workgroups (same numbering as the table index)
+// whose owned cells lie within k of this one's, i.e. those it exchanges
+// halos with.
+struct alignas(16) WgDesc {
+    int32_t prob;
+    int32_t ext_r0, ext_c0;
+    int32_t own_r0, own_r1, own_c0, own_c1;
+    int32_t nnb;
+    int32_t nb[kMaxNeighbours];
+};
+
+}  // namespace dtb

@@ -1,0 +1,215 @@
+"""ctypes binding for libdtb (include/dtb.h): argument marshalling only.
+
+Every computation happens in the HIP kernels of libdtb.so.  If the library is
+missing this module raises; there is no other code path.
+
+Grids are torch tensors on a ROCm device, shape (rows + 2, pitch) --
+interior [1:rows+1, 1:cols+1], one-cell Dirichlet halo -- of dtype float64
+(DTB_F64) or float32 (DTB_F32).  ``cols`` defaults to ``pitch - 2``.
+Coefficients are (c, n, s, e, w).  Work is enqueued on torch's current
+stream unless a stream is given.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdtb.so")
+
+F64, F32 = 0, 1
+PATH_AUTO, PATH_STEP, PATH_RESIDENT, PATH_SWEEP = 0, 1, 2, 3
+STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID_ARG", -2: "DTB_ERR_UNSUPPORTED", -3: "DTB_ERR_NOT_CORESIDENT",
+          -4: "DTB_ERR_OUT_OF_MEMORY", -5: "DTB_ERR_HIP", -6: "DTB_ERR_TIMEOUT", -7: "DTB_ERR_NOT_PLANNED",
+          -8: "DTB_ERR_MISMATCH"}
+DESCRIBE_FIELDS = ("path", "workgroups", "ghost_k", "depth_D", "ext_rows", "ext_cols", "tiles_rows",
+                   "tiles_cols", "rows_per_lane", "cols_per_lane", "big_tiles", "exact")
+TEST_MAX_NEIGHBOURS = 24
+TEST_LAYOUT_STRIDE = 8 + TEST_MAX_NEIGHBOURS
+
+
+class DtbError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)}" if what else STATUS.get(status, str(status)))
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("pitch", ctypes.c_int64)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("ghost_k", ctypes.c_int32), ("depth_D", ctypes.c_int32),
+                ("rows_per_lane", ctypes.c_int32), ("max_wg", ctypes.c_int32), ("exact", ctypes.c_int32),
+                ("debug_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("coeffs", ctypes.c_double * 5), ("T", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+# Every symbol include/dtb.h and include/dtb_testing.h declare.
+EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
+           "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout")
+
+_lib = None
+
+
+def load():
+    """Load libdtb.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing: run __graft_entry__.build() (or python -m paper_2306_03336_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.dtb_plan.restype = ctypes.c_int
+    lib.dtb_plan.argtypes = [ctypes.POINTER(P), ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                             ctypes.c_int64, ctypes.POINTER(PlanOpts)]
+    lib.dtb_run_plan.restype = ctypes.c_int
+    lib.dtb_run_plan.argtypes = [P, ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, P]
+    lib.dtb_run.restype = ctypes.c_int
+    lib.dtb_run.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int, P]
+    lib.dtb_run_batched.restype = ctypes.c_int
+    lib.dtb_run_batched.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, P]
+    lib.dtb_plan_check.restype = ctypes.c_int
+    lib.dtb_plan_check.argtypes = [P, P]
+    lib.dtb_plan_describe.restype = ctypes.c_int
+    lib.dtb_plan_describe.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    lib.dtb_plan_destroy.restype = None
+    lib.dtb_plan_destroy.argtypes = [P]
+    lib.dtb_cache_clear.restype = None
+    lib.dtb_cache_clear.argtypes = []
+    lib.dtb_status_string.restype = ctypes.c_char_p
+    lib.dtb_status_string.argtypes = [ctypes.c_int]
+    lib.dtb_test_layout.restype = ctypes.c_int32
+    lib.dtb_test_layout.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    _lib = lib
+    return lib
+
+
+def status_string(s: int) -> str:
+    return load().dtb_status_string(int(s)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise DtbError(rc, what)
+
+
+def _coeffs(coeffs):
+    c = [float(x) for x in coeffs]
+    if len(c) != 5:
+        raise ValueError("five coefficients (c, n, s, e, w) are required")
+    return (ctypes.c_double * 5)(*c)
+
+
+def _dtype_of(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _grid(t, cols=None) -> Grid:
+    if t.dim() != 2 or not t.is_cuda:
+        raise ValueError("grid must be a 2-D device tensor of shape (rows + 2, pitch)")
+    if t.stride(1) != 1:
+        raise ValueError("grid rows must be contiguous")
+    rows = t.shape[0] - 2
+    pitch = t.stride(0)
+    cols = t.shape[1] - 2 if cols is None else int(cols)
+    return Grid(t.data_ptr(), rows, cols, pitch)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """An explicit plan (dtb_plan / dtb_run_plan / dtb_plan_destroy)."""
+
+    def __init__(self, rows: int, cols: int, pitch: int, dtype: int, T_hint: int = 0, path: int = PATH_AUTO,
+                 ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0, exact: bool = False):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, 0, 0)
+        _check(lib.dtb_plan(ctypes.byref(self._h), rows, cols, pitch, dtype, T_hint, ctypes.byref(opts)), "dtb_plan")
+        self.rows, self.cols, self.pitch, self.dtype = rows, cols, pitch, dtype
+
+    def run(self, grid, coeffs, T: int, stream=None, cols=None):
+        g = _grid(grid, cols)
+        _check(load().dtb_run_plan(self._h, ctypes.byref(g), _coeffs(coeffs), int(T), _stream(stream)),
+               "dtb_run_plan")
+
+    def check(self, stream=None):
+        _check(load().dtb_plan_check(self._h, _stream(stream)), "dtb_plan_check")
+
+    def describe(self) -> dict:
+        vals = (ctypes.c_int64 * len(DESCRIBE_FIELDS))()
+        _check(load().dtb_plan_describe(self._h, vals, len(DESCRIBE_FIELDS)), "dtb_plan_describe")
+        return dict(zip(DESCRIBE_FIELDS, (int(v) for v in vals)))
+
+    def destroy(self):
+        if self._h:
+            load().dtb_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def plan_for(grid, T_hint: int = 0, cols=None, **opts) -> Plan:
+    g = _grid(grid, cols)
+    return Plan(g.rows, g.cols, g.pitch, _dtype_of(grid), T_hint, **opts)
+
+
+def run(grid, coeffs, T: int, stream=None, cols=None):
+    """dtb_run: advance `grid` T steps in place with a cached default plan."""
+    g = _grid(grid, cols)
+    _check(load().dtb_run(ctypes.byref(g), _coeffs(coeffs), int(T), _dtype_of(grid), _stream(stream)), "dtb_run")
+
+
+def run_batched(problems, stream=None):
+    """dtb_run_batched over [(grid, coeffs, T), ...]."""
+    arr = (Problem * len(problems))()
+    for i, (grid, coeffs, T) in enumerate(problems):
+        arr[i].grid = _grid(grid)
+        arr[i].coeffs = _coeffs(coeffs)
+        arr[i].T = int(T)
+        arr[i].dtype = _dtype_of(grid)
+    _check(load().dtb_run_batched(arr, len(problems), _stream(stream)), "dtb_run_batched")
+
+
+def cache_clear():
+    load().dtb_cache_clear()
+
+
+def test_layout(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, waves: int, k: int,
+                n_xcd: int = 8, max_wg: int = 4096):
+    """Planner layout without a GPU: list of dicts per workgroup in launch order (or None)."""
+    buf = (ctypes.c_int32 * (max_wg * TEST_LAYOUT_STRIDE))()
+    n = load().dtb_test_layout(rows, cols, rows_per_lane, cols_per_lane, waves, k, n_xcd, buf, max_wg)
+    if n < 0 or n > max_wg:
+        return None
+    out = []
+    for i in range(n):
+        o = buf[i * TEST_LAYOUT_STRIDE:(i + 1) * TEST_LAYOUT_STRIDE]
+        out.append(dict(ext_r0=o[0], ext_c0=o[1], own_r0=o[2], own_r1=o[3], own_c0=o[4], own_c1=o[5],
+                        nb=[x for x in o[7:7 + o[6]]], narrow_rows=bool(o[7 + TEST_MAX_NEIGHBOURS] & 1),
+                        narrow_cols=bool(o[7 + TEST_MAX_NEIGHBOURS] & 2)))
+    return out

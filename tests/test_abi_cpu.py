@@ -1,0 +1,80 @@
+"""libdtb's C ABI without a GPU: it loads, exports what include/*.h declares,
+and rejects invalid arguments before making any HIP call."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2306_03336_amd import dtb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(dtb_[a-z_]+)\s*\(", text))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    lib = dtb.load()
+    declared = _declared()
+    assert {"dtb_plan", "dtb_run", "dtb_run_batched", "dtb_plan_destroy", "dtb_status_string"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(dtb.EXPORTS)
+
+
+def test_status_strings():
+    for code, name in dtb.STATUS.items():
+        assert dtb.status_string(code) == name
+    assert dtb.status_string(-99) == "DTB_ERR_UNKNOWN"
+
+
+def _plan_rc(rows, cols, pitch, dtype, opts=None, out=True):
+    lib = dtb.load()
+    h = ctypes.c_void_p()
+    o = ctypes.byref(opts) if opts is not None else None
+    return lib.dtb_plan(ctypes.byref(h) if out else None, rows, cols, pitch, dtype, 0, o)
+
+
+@pytest.mark.parametrize("args", [(0, 5, 7, 0), (5, 0, 7, 0), (5, 5, 6, 0), (5, 5, 7, 2), (-1, 5, 7, 1)])
+def test_plan_rejects_bad_shape(args):
+    assert _plan_rc(*args) == -1
+
+
+def test_plan_rejects_null_out_and_bad_options():
+    assert _plan_rc(5, 5, 7, 0, out=False) == -1
+    for field, value in [("path", 9), ("ghost_k", -1), ("exact", 2), ("debug_flags", 1), ("max_wg", -3)]:
+        o = dtb.PlanOpts()
+        setattr(o, field, value)
+        assert _plan_rc(5, 5, 7, 0, o) == -1, field
+
+
+def test_run_rejects_bad_arguments():
+    lib = dtb.load()
+    c = (ctypes.c_double * 5)(0.2, 0.2, 0.2, 0.2, 0.2)
+    g = dtb.Grid(0, 5, 5, 7)
+    assert lib.dtb_run(ctypes.byref(g), c, 3, 0, None) == -1          # NULL data
+    g = dtb.Grid(0x1000, 5, 5, 7)
+    assert lib.dtb_run(ctypes.byref(g), c, -1, 0, None) == -1         # T < 0
+    assert lib.dtb_run(None, c, 3, 0, None) == -1
+    assert lib.dtb_run(ctypes.byref(g), None, 3, 0, None) == -1
+    assert lib.dtb_run(ctypes.byref(g), c, 3, 5, None) == -1          # dtype
+    g = dtb.Grid(0x1000, 5, 5, 6)
+    assert lib.dtb_run(ctypes.byref(g), c, 3, 0, None) == -1          # pitch
+    g = dtb.Grid(0x1000, 5, 5, 7)
+    assert lib.dtb_run(ctypes.byref(g), c, 0, 0, None) == 0           # T == 0: no-op, no HIP call
+    assert lib.dtb_run_batched(None, -1, None) == -1
+    assert lib.dtb_run_batched(None, 0, None) == 0
+    p = (dtb.Problem * 1)()
+    p[0].grid = dtb.Grid(0, 5, 5, 7)
+    assert lib.dtb_run_batched(p, 1, None) == -1
+    assert lib.dtb_run_plan(None, ctypes.byref(g), c, 1, None) == -1
+    assert lib.dtb_plan_check(None, None) == -1
+    lib.dtb_plan_destroy(None)

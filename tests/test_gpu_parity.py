@@ -1,0 +1,246 @@
+"""GPU parity: libdtb (through its C ABI) against the CPU oracle.
+
+Exact mode (separately rounded products summed W, E, S, C, N) must match the
+oracle bit for bit -- FP64 against the FP64 oracle, FP32 against the FP32
+oracle.  The default fused chain must stay within 1e-13 relative max-norm of
+the FP64 oracle.  Every case prints its parameters before it touches the GPU.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_03336_amd import dtb, inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL_F64 = 1e-13
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(u):
+    return torch.from_numpy(np.ascontiguousarray(u)).to("cuda")
+
+
+def _random_halo(u, rng, rows, cols):
+    u[0, :cols + 2] = rng.uniform(-1, 2, cols + 2)
+    u[rows + 1, :cols + 2] = rng.uniform(-1, 2, cols + 2)
+    u[:, 0] = rng.uniform(-1, 2, rows + 2)
+    u[:, cols + 1] = rng.uniform(-1, 2, rows + 2)
+    return u
+
+
+def _run_plan(u, coeffs, T, dtype=np.float64, cols=None, **opts):
+    g = _dev(u.astype(dtype))
+    plan = dtb.plan_for(g, T, cols=cols, **opts)
+    plan.run(g, coeffs, T, cols=cols)
+    plan.check()
+    desc = plan.describe()
+    out = g.cpu().numpy()
+    plan.destroy()
+    return out, desc
+
+
+SHAPES = [(1, 1), (1, 37), (45, 1), (3, 200), (127, 131), (256, 256), (200, 300), (70, 130), (129, 257)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("R", [8, 16, 24])
+def test_exact_f64_bitwise(shape, R):
+    rows, cols = shape
+    rng = np.random.default_rng(rows * 1000 + cols + R)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols)
+    for k, T in [(1, 3), (2, 7), (4, 4), (5, 23), (8, 37), (16, 9)]:
+        _say("exact f64", rows, cols, "R", R, "k", k, "T", T)
+        try:
+            got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_RESIDENT, ghost_k=k, rows_per_lane=R, exact=True)
+        except dtb.DtbError as e:
+            assert e.status == -3 and 2 * k >= 64, (rows, cols, R, k, e)  # ring deeper than the tile
+            continue
+        ref = oracle.j2d5pt_f64(u, coeffs, T)
+        assert desc["path"] == dtb.PATH_RESIDENT and desc["exact"] == 1
+        assert np.array_equal(got, ref), (rows, cols, R, k, T, float(np.max(np.abs(got - ref))))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (40, 1), (2, 300), (131, 127), (256, 256), (90, 520)],
+                         ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("R", [8, 24])
+def test_exact_f32_bitwise(shape, R):
+    rows, cols = shape
+    rng = np.random.default_rng(rows * 7 + cols + R)
+    coeffs = (0.05, 0.4, 0.01, 0.5, 0.04)  # strongly asymmetric: drives cells into subnormals
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(np.float32)
+    for k, T in [(2, 5), (6, 40), (8, 200)]:
+        _say("exact f32", rows, cols, "R", R, "k", k, "T", T)
+        got, _ = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_RESIDENT, ghost_k=k,
+                           rows_per_lane=R, exact=True)
+        ref = oracle.j2d5pt_f32(u, coeffs, T)
+        assert np.array_equal(got, ref), (rows, cols, R, k, T)
+
+
+def test_exact_f32_keeps_subnormals():
+    rows, cols = 64, 300
+    coeffs = (0.05, 0.4, 0.01, 0.5, 0.04)
+    u = inputs.uniform_grid(rows, cols, 3).astype(np.float32)
+    T = 400
+    _say("f32 subnormals", rows, cols, T)
+    got, _ = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_RESIDENT, exact=True)
+    ref = oracle.j2d5pt_f32(u, coeffs, T)
+    tiny = np.finfo(np.float32).tiny
+    sub = (ref[1:-1, 1:-1] != 0) & (np.abs(ref[1:-1, 1:-1]) < tiny)
+    assert sub.any(), "the case should produce subnormal values"
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (127, 131), (300, 700)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_step_path_bitwise_and_matches_dtb_fma(shape):
+    rows, cols = shape
+    rng = np.random.default_rng(5)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols)
+    for T in (1, 2, 9):
+        _say("step path", rows, cols, "T", T)
+        got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_STEP, exact=True)
+        assert desc["path"] == dtb.PATH_STEP
+        assert np.array_equal(got, oracle.j2d5pt_f64(u, coeffs, T))
+        step_fma, _ = _run_plan(u, coeffs, T, path=dtb.PATH_STEP)
+        dtb_fma, _ = _run_plan(u, coeffs, T, path=dtb.PATH_RESIDENT, ghost_k=4)
+        assert np.array_equal(step_fma, dtb_fma)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fma_default_within_tolerance(dtype):
+    rows, cols, T = 600, 700, 300
+    coeffs = inputs.dirichlet_weights(17)
+    u = inputs.uniform_grid(rows, cols, 18, halo=0.5)
+    _say("fma default", dtype, rows, cols, T)
+    npd = np.float64 if dtype == "f64" else np.float32
+    got, desc = _run_plan(u.astype(npd), coeffs, T)
+    assert desc["exact"] == 0
+    ref = oracle.j2d5pt_f64(u, coeffs, T)
+    err = oracle.rel_max_err(got, ref)
+    print(f"[result] {dtype} fused chain rel max err vs FP64 oracle: {err:.3e}")
+    if dtype == "f64":
+        assert err <= TOL_F64
+    else:
+        assert err <= 2e-5
+
+
+def test_halo_and_pitch_padding_untouched():
+    rows, cols, pitch = 150, 140, 150
+    u = inputs.uniform_grid(rows, cols, 4, halo=0.25, pitch=pitch)
+    u[:, cols + 2:] = -777.0
+    _say("padding", rows, cols, pitch)
+    got, _ = _run_plan(u, inputs.EQUAL_WEIGHTS, 11, cols=cols, path=dtb.PATH_RESIDENT, ghost_k=3, exact=True)
+    assert np.array_equal(got[:, cols + 2:], u[:, cols + 2:])
+    assert np.array_equal(got[0], u[0]) and np.array_equal(got[-1], u[-1])
+    assert np.array_equal(got[:, 0], u[:, 0]) and np.array_equal(got[:, cols + 1], u[:, cols + 1])
+    ref = oracle.j2d5pt_f64(u, inputs.EQUAL_WEIGHTS, 11, cols=cols)
+    assert np.array_equal(got, ref)
+
+
+def test_semigroup_and_determinism():
+    rows, cols = 333, 444
+    coeffs = inputs.dirichlet_weights(21)
+    u = inputs.uniform_grid(rows, cols, 22)
+    _say("semigroup", rows, cols)
+    g = _dev(u)
+    plan = dtb.plan_for(g, 0, ghost_k=6)
+    plan.run(g, coeffs, 25)
+    plan.run(g, coeffs, 40)
+    plan.check()
+    split = g.cpu().numpy()
+    g2 = _dev(u)
+    plan.run(g2, coeffs, 65)
+    plan.check()
+    assert np.array_equal(split, g2.cpu().numpy())
+    g3 = _dev(u)
+    plan.run(g3, coeffs, 65)
+    plan.check()
+    assert np.array_equal(g3.cpu().numpy(), g2.cpu().numpy())
+    # a different tiling (k, rows per lane) gives the same bits: the chain per cell is fixed
+    other, _ = _run_plan(u, coeffs, 65, ghost_k=2, rows_per_lane=8)
+    assert np.array_equal(other, split)
+
+
+def test_T0_and_cached_run():
+    rows, cols = 100, 90
+    u = inputs.uniform_grid(rows, cols, 23)
+    g = _dev(u)
+    _say("cached run", rows, cols)
+    dtb.run(g, inputs.EQUAL_WEIGHTS, 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cpu().numpy(), u)
+    dtb.run(g, inputs.EQUAL_WEIGHTS, 13)
+    dtb.run(g, inputs.EQUAL_WEIGHTS, 13)
+    torch.cuda.synchronize()
+    ref = oracle.j2d5pt_f64(u, inputs.EQUAL_WEIGHTS, 26)
+    assert oracle.rel_max_err(g.cpu().numpy(), ref) <= TOL_F64
+
+
+def test_batched_matches_single_runs():
+    rng = np.random.default_rng(31)
+    probs, refs = [], []
+    for i, side in enumerate([130, 257, 64, 400]):
+        coeffs = inputs.dirichlet_weights(rng)
+        u = inputs.uniform_grid(side, side, rng)
+        T = int(rng.integers(5, 60))
+        dt = np.float64 if i % 2 == 0 else np.float32
+        probs.append((_dev(u.astype(dt)), coeffs, T))
+        refs.append(oracle.j2d5pt_f64(u.astype(dt).astype(np.float64), np.array(coeffs, dtype=dt).astype(np.float64), T))
+    _say("batched", len(probs))
+    dtb.run_batched(probs)
+    torch.cuda.synchronize()
+    for (g, coeffs, T), ref in zip(probs, refs):
+        err = oracle.rel_max_err(g.cpu().numpy(), ref)
+        assert err <= (TOL_F64 if g.dtype == torch.float64 else 2e-5), err
+
+
+@pytest.mark.slow
+def test_full_size_2048_T10000_against_oracle():
+    """The benchmark's workload and launch configuration, whole grid, all 10000 steps."""
+    w = inputs.workload("j2d5pt_2048x2048_f64_T10000")
+    u0 = w.grid()
+    _say("full size", w.name)
+    g = _dev(u0)
+    plan = dtb.plan_for(g, w.T)
+    plan.run(g, w.coeffs, w.T)
+    plan.check()
+    got = g.cpu().numpy()
+    desc = plan.describe()
+    ref = oracle.j2d5pt_f64(u0, w.coeffs, w.T)
+    err = oracle.rel_max_err(got, ref)
+    print(f"[result] {w.name} plan={desc} rel max err {err:.3e}")
+    assert desc["path"] == dtb.PATH_RESIDENT
+    assert err <= TOL_F64
+    assert np.array_equal(got[0], u0[0]) and np.array_equal(got[:, 0], u0[:, 0])
+
+
+def test_sine_mode_full_size_closed_form():
+    """2048^2, 10000 steps of a single sine mode against its closed-form decay (symmetrised weights)."""
+    rows = cols = 2048
+    c, n, s, e, w = inputs.workload("j2d5pt_2048x2048_f64_T10000").coeffs
+    for coeffs in [(c, (n + s) / 2, (n + s) / 2, (e + w) / 2, (e + w) / 2), inputs.EQUAL_WEIGHTS]:
+        u0 = inputs.sine_grid(rows, cols)
+        T = 10000
+        _say("sine mode", coeffs)
+        g = _dev(u0)
+        plan = dtb.plan_for(g, T)
+        plan.run(g, coeffs, T)
+        plan.check()
+        got = g.cpu().numpy()
+        cc, nn, ss, ee, ww = coeffs
+        lam = cc + 2 * math.sqrt(nn * ss) * math.cos(math.pi / (rows + 1)) + 2 * math.sqrt(ee * ww) * math.cos(
+            math.pi / (cols + 1))
+        want = u0 * math.exp(T * math.log(lam))
+        err = np.max(np.abs(got[1:-1, 1:-1] - want[1:-1, 1:-1])) / np.max(np.abs(want[1:-1, 1:-1]))
+        print(f"[result] sine mode lambda^T={lam ** T:.6f} rel err {err:.3e}")
+        assert err < 1e-11

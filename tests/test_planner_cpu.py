@@ -1,0 +1,80 @@
+"""The resident-path tile planner, run on the host without a GPU (dtb_test_layout).
+
+Checks, for many shapes: owned regions tile the interior exactly; each tile's
+k-deep fresh ring lies inside its register tile; register tiles stay inside
+the storage; neighbour lists are exactly the tiles within k (and symmetric);
+XCD grouping keeps most exchanges inside one XCD.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2306_03336_amd import dtb
+
+SHAPES = [(1, 1), (1, 200), (200, 1), (127, 131), (256, 256), (300, 129), (129, 257), (1000, 777),
+          (2048, 2048), (3072, 3072)]
+INSTANCES = [(8, 2, 8), (16, 2, 8), (24, 2, 8), (16, 4, 8), (24, 4, 8)]  # rows/lane, cols/lane, waves
+
+
+def _check_layout(rows, cols, R, C, waves, k, lay):
+    ER, EC = waves * R, 64 * C
+    owner = np.full((rows + 2, cols + 2), -1, dtype=np.int64)
+    for a, d in enumerate(lay):
+        assert 1 <= d["own_r0"] < d["own_r1"] <= rows + 1 and 1 <= d["own_c0"] < d["own_c1"] <= cols + 1
+        blk = owner[d["own_r0"]:d["own_r1"], d["own_c0"]:d["own_c1"]]
+        assert np.all(blk == -1), "owned regions overlap"
+        blk[...] = a
+        # fresh ring inside the register tile
+        f_r0, f_r1 = max(d["own_r0"] - k, 1), min(d["own_r1"] + k, rows + 1)
+        f_c0, f_c1 = max(d["own_c0"] - k, 1), min(d["own_c1"] + k, cols + 1)
+        assert d["ext_r0"] <= f_r0 and f_r1 <= d["ext_r0"] + ER
+        assert d["ext_c0"] <= f_c0 and f_c1 <= d["ext_c0"] + EC
+        assert d["ext_r0"] >= 1 and d["ext_c0"] >= 1
+        if not d["narrow_rows"]:
+            assert d["ext_r0"] + ER - 1 <= rows
+        if not d["narrow_cols"]:
+            assert d["ext_c0"] + EC - 1 <= cols
+        assert d["narrow_rows"] == (rows < ER) and d["narrow_cols"] == (cols < EC)
+    assert np.all(owner[1:rows + 1, 1:cols + 1] >= 0), "interior not covered"
+    for a, d in enumerate(lay):
+        f = owner[max(d["own_r0"] - k, 1):min(d["own_r1"] + k, rows + 1),
+                  max(d["own_c0"] - k, 1):min(d["own_c1"] + k, cols + 1)]
+        want = sorted(set(np.unique(f).tolist()) - {a})
+        assert sorted(d["nb"]) == want
+    for a, d in enumerate(lay):
+        for b in d["nb"]:
+            assert a in lay[b]["nb"]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("inst", INSTANCES, ids=lambda i: f"R{i[0]}C{i[1]}")
+@pytest.mark.parametrize("k", [1, 2, 5, 8, 16])
+def test_layout_properties(shape, inst, k):
+    rows, cols = shape
+    R, C, waves = inst
+    lay = dtb.test_layout(rows, cols, R, C, waves, k, 8, max_wg=8192)
+    if lay is None:
+        # only impossible when the ghost ring does not fit the register tile
+        assert 2 * k >= min(waves * R, 64 * C) and (rows > waves * R or cols > 64 * C)
+        return
+    _check_layout(rows, cols, R, C, waves, k, lay)
+
+
+def test_config_2048_fits_one_wave_of_workgroups():
+    lay = dtb.test_layout(2048, 2048, 24, 2, 8, 8)
+    assert lay is not None and len(lay) <= 256
+
+
+def test_xcd_grouping_keeps_exchanges_local():
+    lay = dtb.test_layout(2048, 2048, 24, 2, 8, 8)
+    n = len(lay)
+    cross = sum(1 for a, d in enumerate(lay) for b in d["nb"] if a % 8 != b % 8)
+    total = sum(len(d["nb"]) for d in lay)
+    assert cross < 0.35 * total
+    # a plain row-major deal would put almost every neighbour on another XCD
+    assert total > 0 and n > 8
+
+
+def test_no_layout_when_ring_too_deep():
+    assert dtb.test_layout(4096, 4096, 8, 2, 8, 40) is None
