@@ -21,7 +21,7 @@ namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // bounded wait: a few seconds of polling
 constexpr int kNumXcd = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
-constexpr int kDtbRowsPerLane[] = {8, 16, 24};
+constexpr int kDtbRowsPerLane[] = {8, 16, 20, 24};  // instantiated: FP64 8, 16, 24; FP32 8, 16, 20
 
 struct DeviceInfo {
     int device = -1;

@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dtb_internal.h"
 
 namespace dtb {
@@ -110,17 +112,17 @@ __global__ __launch_bounds__(256) void k_copy_interior(const T* __restrict__ src
 
 // ============================================================================ deep temporal blocking
 
-// DPP wave shifts (GFX9 wave_shr:1 / wave_shl:1).  Lanes whose source lane
-// does not exist (lane 0 for shr, lane 63 for shl) keep `old`.
+// DPP wave shifts (GFX9 wave_shr:1 / wave_shl:1) with bound_ctrl: a lane
+// whose source lane does not exist (lane 0 for shr, lane 63 for shl) reads 0.
 template <typename T>
-__device__ __forceinline__ T wave_shr1(T old, T v)
+__device__ __forceinline__ T wave_shr1(T v)
 {
-    return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp((T)0, v, 0x138, 0xf, 0xf, true);
 }
 template <typename T>
-__device__ __forceinline__ T wave_shl1(T old, T v)
+__device__ __forceinline__ T wave_shl1(T v)
 {
-    return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp((T)0, v, 0x130, 0xf, 0xf, true);
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -128,16 +130,53 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // Wrap-safe "counter a has reached b".
 __device__ __forceinline__ bool reached(uint32_t a, uint32_t b) { return (int32_t)(a - b) >= 0; }
 
+// The update with the west and east products given an addend: lane 0 of a
+// west-edge tile reads W = 0 from the shift and gets the halo product w*hW
+// as the addend of its first product; lane 63 of an east-edge tile likewise
+// gets e*hE.  Everywhere else the addends are 0, so fma(w, W, 0) is just the
+// rounded product and both modes keep their operation order:
+//   FMA:   acc = fma(w, W, bw + be); then e, s, c, n by fused multiply-adds;
+//   exact: acc = fma(w, W, bw); p = fma(e, E, be); acc += p; acc += s*S; acc += c*C; acc += n*N.
+template <bool FMA, bool BW, bool BE, typename T>
+__device__ __forceinline__ T j2d5pt_edge(T W, T E, T S, T C, T N, T bw, T be, T bwe, const Coef<T>& k)
+{
+    if constexpr (FMA) {
+        T acc;
+        if constexpr (BW && BE) acc = __builtin_fma(k.w, W, bwe);
+        else if constexpr (BW) acc = __builtin_fma(k.w, W, bw);
+        else if constexpr (BE) acc = __builtin_fma(k.w, W, be);
+        else acc = k.w * W;
+        acc = __builtin_fma(k.e, E, acc);
+        acc = __builtin_fma(k.s, S, acc);
+        acc = __builtin_fma(k.c, C, acc);
+        acc = __builtin_fma(k.n, N, acc);
+        return acc;
+    } else {
+        T acc;
+        if constexpr (BW) acc = __builtin_fma(k.w, W, bw);
+        else acc = k.w * W;
+        T pe;
+        if constexpr (BE) pe = __builtin_fma(k.e, E, be);
+        else pe = k.e * E;
+        acc = acc + pe;
+        acc = acc + k.s * S;
+        acc = acc + k.c * C;
+        acc = acc + k.n * N;
+        return acc;
+    }
+}
+
 // Geometry of one kernel instance: C columns x R rows per lane, WAVES waves
 // stacked vertically.  Extended tile: (WAVES * R) x (64 * C) cells.
 template <typename T, int C, int R, int WAVES>
 struct Geo {
     static constexpr int ER = WAVES * R;
     static constexpr int EC = kWaveSize * C;
-    // LDS: edge rows [parity][slot = wave + 1][top/bottom][64 * C] and, per
-    // extended row, the west/east halo values for lanes 0 and 63.
+    // LDS: edge rows [parity][slot = wave + 1][top/bottom][64 * C], then per
+    // extended row the west and east halo products (w*hW, e*hE) and a row of
+    // zeros (what every other lane reads on the row-by-row halo path).
     static constexpr int kEdgeElems = 2 * (WAVES + 2) * 2 * EC;
-    static constexpr int kHaloElems = ER * 2;
+    static constexpr int kHaloElems = ER * 3;
     static constexpr size_t kLdsBytes = (size_t)(kEdgeElems + kHaloElems) * sizeof(T);
 };
 
@@ -150,13 +189,16 @@ struct Tile {
     T a[R][C];
     T b[R][C];
 
-    T* edge;   // LDS
-    T* halo;   // LDS
+    T* edge;         // LDS edge rows
+    const T* hbw;    // LDS, per lane: the west products (lane 0) or zeros
+    const T* hbe;    // LDS, per lane: the east products (lane 63) or zeros
+    const T* hbwe;   // LDS, per lane: lane 0 west, lane 63 east, zeros elsewhere
     int wave, lane;
-    int g0;        // storage row of this wave's row 0
-    int col0;      // storage column of this lane's slot 0
+    int g0;          // storage row of this wave's row 0
+    int col0;        // storage column of this lane's slot 0
     bool colact[C];
     Coef<T> k;
+    T bw, be, bwe;   // halo addends when they are the same for every row
 
     __device__ __forceinline__ T* edge_row(int parity, int slot, int bottom)
     {
@@ -164,6 +206,9 @@ struct Tile {
     }
 
     // One time step: src -> dst.  `parity` selects the LDS edge buffer.
+    // HALO_ROWS: the halo addends change from row to row (an edge tile of a
+    // grid whose west/east halo is not constant) and are read from LDS.
+    template <bool HALO_ROWS>
     __device__ __forceinline__ void step(T (&src)[R][C], T (&dst)[R][C], int parity, int rows)
     {
         // Publish this wave's current top and bottom rows for the waves above and below.
@@ -183,33 +228,49 @@ struct Tile {
             top[c] = above[c];
             bot[c] = below[c];
         }
-        const T* hrow = halo + (size_t)wave * R * 2;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (ROWCHECK) {
                 const int g = g0 + r;
                 if (g < 1 || g > rows) continue;
             }
-            const T hw = hrow[2 * r];
-            const T he = hrow[2 * r + 1];
-            const T wlane = wave_shr1(hw, src[r][C - 1]);  // west neighbour of slot 0
-            const T elane = wave_shl1(he, src[r][0]);      // east neighbour of slot C-1
+            T rbw = bw, rbe = be, rbwe = bwe;
+            if constexpr (HALO_ROWS) {
+                rbw = hbw[wave * R + r];
+                rbe = hbe[wave * R + r];
+                rbwe = hbwe[wave * R + r];
+            }
+            const T wlane = wave_shr1(src[r][C - 1]);  // west neighbour of slot 0
+            const T elane = wave_shl1(src[r][0]);      // east neighbour of slot C-1
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const T Wv = (c == 0) ? wlane : src[r][c - 1];
                 const T Ev = (c == C - 1) ? elane : src[r][c + 1];
                 const T Sv = (r == 0) ? top[c] : src[r - 1][c];
                 const T Nv = (r == R - 1) ? bot[c] : src[r + 1][c];
-                T v = j2d5pt<FMA>(Wv, Ev, Sv, src[r][c], Nv, k);
+                T v;
+                if (c == 0 && c == C - 1)
+                    v = j2d5pt_edge<FMA, true, true>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+                else if (c == 0)
+                    v = j2d5pt_edge<FMA, true, false>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+                else if (c == C - 1)
+                    v = j2d5pt_edge<FMA, false, true>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+                else
+                    v = j2d5pt_edge<FMA, false, false>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
                 if constexpr (COLMASK) v = colact[c] ? v : dst[r][c];
                 dst[r][c] = v;
             }
+            // The row-by-row halo path is rare (edge tiles with a varying
+            // halo); keep the scheduler from hoisting every row's LDS reads,
+            // which would cost a register pair per row.
+            if constexpr (HALO_ROWS) __builtin_amdgcn_sched_barrier(0);
         }
     }
 
     // The owned cells within k of an owned edge: what the neighbours need.
-    __device__ __forceinline__ void publish(T (&x)[R][C], T* __restrict__ xb, int64_t pitch,
-                                            const WgDesc& d, int kk)
+    // Written with device-scope (sc1) stores, which are coherent across XCDs
+    // without an L2 write-back.
+    __device__ __forceinline__ void publish(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk)
     {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -221,14 +282,17 @@ struct Tile {
                 const int col = col0 + c;
                 const bool own = col >= d.own_c0 && col < d.own_c1;
                 const bool near = row_near || col < d.own_c0 + kk || col >= d.own_c1 - kk;
-                if (own && near) xb[(int64_t)g * pitch + col] = x[r][c];
+                if (own && near)
+                    __hip_atomic_store(xb + (int64_t)g * pitch + col, x[r][c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
 
-    // Refresh the ghost ring (cells within k of the owned region, inside the interior, not owned).
-    __device__ __forceinline__ void load_ghost(T (&x)[R][C], const T* __restrict__ xb, int64_t pitch,
-                                               const WgDesc& d, int kk, int rows, int cols)
+    // Refresh the ghost ring (cells within k of the owned region, inside the
+    // interior, not owned) with device-scope (sc1) loads.
+    __device__ __forceinline__ void load_ghost(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk,
+                                               int rows, int cols)
     {
         const int r_lo = max(d.own_r0 - kk, 1), r_hi = min(d.own_r1 + kk, rows + 1);
         const int c_lo = max(d.own_c0 - kk, 1), c_hi = min(d.own_c1 + kk, cols + 1);
@@ -242,7 +306,9 @@ struct Tile {
                 const int col = col0 + c;
                 const bool in_ring = col >= c_lo && col < c_hi;
                 const bool own = row_own && col >= d.own_c0 && col < d.own_c1;
-                if (in_ring && !own) x[r][c] = xb[(int64_t)g * pitch + col];
+                if (in_ring && !own)
+                    x[r][c] = __hip_atomic_load(xb + (int64_t)g * pitch + col, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -263,17 +329,22 @@ struct Tile {
     }
 };
 
-// Neighbour-wise bulk-synchronous exchange point.  Every thread's prior global
-// stores are released at agent scope, one thread raises this workgroup's
-// epoch flag, and the first nnb threads of wave 0 wait (bounded) until each
-// neighbour's flag has reached the same epoch.  On timeout the error word is
-// set and the wait is abandoned, so the grid always drains.
+// Neighbour-wise bulk-synchronous exchange point.
+//
+// The border strips were written with device-scope atomic stores; waiting for
+// them to complete (vmcnt 0) makes them visible to every XCD, so no L2
+// write-back is needed before this workgroup raises its epoch flag.  The
+// first nnb threads of wave 0 then wait (bounded) until each neighbour's flag
+// has reached the same epoch; the ghost ring is read afterwards with
+// device-scope loads, so no L2 invalidate is needed either.  The inline
+// waits double as compiler barriers (memory clobber).  On timeout the error
+// word is set and the wait is abandoned, so the grid always drains.
 __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const WgDesc& d, uint32_t target,
                                                int* err, uint32_t spin_limit)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flags + me, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(flags + me, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((int)threadIdx.x < d.nnb) {
         const int nb = d.nb[threadIdx.x];
         uint32_t spins = 0;
@@ -284,86 +355,39 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
                 break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
-__device__ __forceinline__ void run_tile(const ProbDesc& P, const WgDesc& d, int me, uint32_t* flags, int* err,
-                                         uint32_t spin_limit, char* lds)
+// All time steps of one tile, the halo addends either fixed (HALO_ROWS =
+// false) or read per row.  The state is in register set a at every epoch
+// boundary: steps go in pairs a -> b -> a (LDS edge parity 0 then 1); an odd
+// tail step is copied back.  A run of k steps is followed by an exchange
+// point (a workgroup barrier), so an odd k never lets two consecutive steps
+// share a parity.
+template <bool HALO_ROWS, typename Tl>
+__device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDesc& d, int me, uint32_t* flags,
+                                           int* err, uint32_t spin_limit)
 {
-    using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>;
-    using G = typename Tl::G;
-    Tl t;
-    T* grid = (T*)P.grid;
+    using T = typename std::remove_reference<decltype(t.a[0][0])>::type;
+    constexpr int R = sizeof(t.a) / sizeof(t.a[0]);
+    constexpr int C = sizeof(t.a[0]) / sizeof(t.a[0][0]);
+    const int rows = P.rows, cols = P.cols, kk = P.k;
     const int64_t pitch = P.pitch;
-    const int rows = P.rows, cols = P.cols;
-    const int kk = P.k;
-    t.edge = (T*)lds;
-    t.halo = (T*)lds + G::kEdgeElems;
-    t.wave = uniform(threadIdx.x >> 6);
-    t.lane = threadIdx.x & 63;
-    t.g0 = d.ext_r0 + t.wave * R;
-    t.col0 = d.ext_c0 + t.lane * C;
-    t.k = load_coef<T>(P.coeffs);
-#pragma unroll
-    for (int c = 0; c < C; ++c) t.colact[c] = (t.col0 + c) <= cols;
-
-    // ---- load the extended tile (both register sets) and the fixed boundary values
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int g = t.g0 + r;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int col = t.col0 + c;
-            const T v = (g <= rows + 1 && col <= cols + 1) ? grid[(int64_t)g * pitch + col] : T(0);
-            t.a[r][c] = v;
-            t.b[r][c] = v;
-        }
-    }
-    // Rows just above and below the extended tile (the halo rows for edge tiles), both parities.
-    {
-        const int gt = d.ext_r0 - 1;
-        const int gb = d.ext_r0 + G::ER;
-        for (int idx = threadIdx.x; idx < G::EC; idx += WAVES * kWaveSize) {
-            const int col = d.ext_c0 + idx;
-            const T vt = (col <= cols + 1) ? grid[(int64_t)gt * pitch + col] : T(0);
-            const T vb = (gb <= rows + 1 && col <= cols + 1) ? grid[(int64_t)gb * pitch + col] : T(0);
-            for (int p = 0; p < 2; ++p) {
-                t.edge_row(p, 0, 1)[idx] = vt;
-                t.edge_row(p, WAVES + 1, 0)[idx] = vb;
-            }
-        }
-        // Columns just west and east of the extended tile, per extended row.
-        for (int idx = threadIdx.x; idx < G::ER; idx += WAVES * kWaveSize) {
-            const int g = d.ext_r0 + idx;
-            const int cw = d.ext_c0 - 1, ce = d.ext_c0 + G::EC;
-            const bool grow = g <= rows + 1;
-            t.halo[2 * idx] = (grow && cw >= 0) ? grid[(int64_t)g * pitch + cw] : T(0);
-            t.halo[2 * idx + 1] = (grow && ce <= cols + 1) ? grid[(int64_t)g * pitch + ce] : T(0);
-        }
-    }
-    __syncthreads();
-
-    uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t epoch = 0;
     int64_t done = 0;
     bool exchanged = false;
-    // The state is in register set a at every epoch boundary: steps go in
-    // pairs a -> b -> a (LDS edge parity 0 then 1); an odd tail step is copied
-    // back.  A run of k steps is followed by an exchange point (a workgroup
-    // barrier), so an odd k never lets two consecutive steps share a parity.
     while (done < P.T) {
         const int64_t left = P.T - done;
         const int nsteps = (int)(left < kk ? left : kk);
         for (int s = 0; s + 1 < nsteps; s += 2) {
-            t.step(t.a, t.b, 0, rows);
-            t.step(t.b, t.a, 1, rows);
+            t.template step<HALO_ROWS>(t.a, t.b, 0, rows);
+            t.template step<HALO_ROWS>(t.b, t.a, 1, rows);
         }
         if (nsteps & 1) {
-            t.step(t.a, t.b, 0, rows);
+            t.template step<HALO_ROWS>(t.a, t.b, 0, rows);
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -385,7 +409,100 @@ __device__ __forceinline__ void run_tile(const ProbDesc& P, const WgDesc& d, int
         ++epoch;
         exchange_point(flags, me, d, base + epoch, err, spin_limit);
     }
-    t.store_owned(t.a, grid, pitch, d);
+    t.store_owned(t.a, (T*)P.grid, pitch, d);
+}
+
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS>
+__device__ __forceinline__ void run_tile(const ProbDesc& P, const WgDesc& d, int me, uint32_t* flags, int* err,
+                                         uint32_t spin_limit, char* lds)
+{
+    using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>;
+    using G = typename Tl::G;
+    Tl t;
+    const T* grid = (const T*)P.grid;
+    const int64_t pitch = P.pitch;
+    const int rows = P.rows, cols = P.cols;
+    t.edge = (T*)lds;
+    T* hx = (T*)lds + G::kEdgeElems;  // [0, ER): w*hW, [ER, 2ER): e*hE, [2ER, 3ER): 0
+    t.wave = uniform(threadIdx.x >> 6);
+    t.lane = threadIdx.x & 63;
+    t.g0 = d.ext_r0 + t.wave * R;
+    t.col0 = d.ext_c0 + t.lane * C;
+    t.k = load_coef<T>(P.coeffs);
+#pragma unroll
+    for (int c = 0; c < C; ++c) t.colact[c] = (t.col0 + c) <= cols;
+
+    // ---- load the extended tile (both register sets) and the fixed boundary values
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int g = t.g0 + r;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int col = t.col0 + c;
+            const T v = (g <= rows + 1 && col <= cols + 1) ? grid[(int64_t)g * pitch + col] : T(0);
+            t.a[r][c] = v;
+            t.b[r][c] = v;
+        }
+    }
+    // Rows just above and below the extended tile (the halo rows for edge
+    // tiles, stale ghost values otherwise), both parities.
+    const int gt = d.ext_r0 - 1;
+    const int gb = d.ext_r0 + G::ER;
+    for (int idx = threadIdx.x; idx < G::EC; idx += WAVES * kWaveSize) {
+        const int col = d.ext_c0 + idx;
+        const T vt = (col <= cols + 1) ? grid[(int64_t)gt * pitch + col] : T(0);
+        const T vb = (gb <= rows + 1 && col <= cols + 1) ? grid[(int64_t)gb * pitch + col] : T(0);
+        for (int p = 0; p < 2; ++p) {
+            t.edge_row(p, 0, 1)[idx] = vt;
+            t.edge_row(p, WAVES + 1, 0)[idx] = vb;
+        }
+    }
+    // West/east halo products for the rows of an edge tile (zero elsewhere:
+    // the outermost ghost columns of an interior tile are expendable).
+    const bool west_edge = d.ext_c0 == 1;
+    const bool east_edge = !COLMASK && d.ext_c0 + G::EC - 1 == cols;
+    for (int idx = threadIdx.x; idx < G::ER; idx += WAVES * kWaveSize) {
+        const int g = d.ext_r0 + idx;
+        const bool grow = g >= 1 && g <= rows;
+        hx[idx] = (west_edge && grow) ? t.k.w * grid[(int64_t)g * pitch] : T(0);
+        hx[G::ER + idx] = (east_edge && grow) ? t.k.e * grid[(int64_t)g * pitch + cols + 1] : T(0);
+        hx[2 * G::ER + idx] = T(0);
+    }
+    __syncthreads();
+
+    // With HALO_ROWS == false the products are the same on every row (checked
+    // by the caller) and live in registers.
+    const T zero = T(0);
+    t.bw = t.lane == 0 ? hx[0] : zero;
+    t.be = t.lane == 63 ? hx[G::ER] : zero;
+    t.bwe = t.lane == 0 ? hx[0] : (t.lane == 63 ? hx[G::ER] : zero);
+    t.hbw = hx + (t.lane == 0 ? 0 : 2 * G::ER);
+    t.hbe = hx + (t.lane == 63 ? G::ER : 2 * G::ER);
+    t.hbwe = hx + (t.lane == 0 ? 0 : (t.lane == 63 ? G::ER : 2 * G::ER));
+
+    run_epochs<HALO_ROWS>(t, P, d, me, flags, err, spin_limit);
+}
+
+// Does the west or east halo of this tile's rows change from row to row?
+// (Only edge tiles look: an interior tile never reads the halo.)
+template <typename T, int C, int R, int WAVES, bool COLMASK>
+__device__ __forceinline__ bool halo_varies(const ProbDesc& P, const WgDesc& d)
+{
+    using G = Geo<T, C, R, WAVES>;
+    const T* grid = (const T*)P.grid;
+    const int rows = P.rows, cols = P.cols;
+    const bool west_edge = d.ext_c0 == 1;
+    const bool east_edge = !COLMASK && d.ext_c0 + G::EC - 1 == cols;
+    bool mine = false;
+    if (west_edge || east_edge) {
+        const int r0 = max(d.ext_r0, 1), r1 = min(d.ext_r0 + G::ER - 1, rows);
+        const T w0 = grid[(int64_t)r0 * P.pitch], e0 = grid[(int64_t)r0 * P.pitch + cols + 1];
+        for (int g = r0 + (int)threadIdx.x; g <= r1; g += WAVES * kWaveSize) {
+            if (west_edge && grid[(int64_t)g * P.pitch] != w0) mine = true;
+            if (east_edge && grid[(int64_t)g * P.pitch + cols + 1] != e0) mine = true;
+        }
+    }
+    return __syncthreads_or(mine);
 }
 
 // LDS for the largest instance a kernel can run.
@@ -403,7 +520,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_dtb(ProbDesc P, const WgDesc* __
     const int me = blockIdx.x;
     const WgDesc& d = wgs[me];
     char* lds = dtb_lds<T, C, R, WAVES>();
-    run_tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>(P, d, me, flags, err, spin_limit, lds);
+    if (halo_varies<T, C, R, WAVES, COLMASK>(P, d))
+        run_tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true>(P, d, me, flags, err, spin_limit, lds);
+    else
+        run_tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false>(P, d, me, flags, err, spin_limit, lds);
 }
 
 // Copies the halo ring of src into dst (so a one-step workspace sees the grid's boundary).
@@ -502,7 +622,7 @@ const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, 
         switch (R) {
         case 8: return pick<float, 4, 8>(fma, colmask, rowcheck);
         case 16: return pick<float, 4, 16>(fma, colmask, rowcheck);
-        case 24: return pick<float, 4, 24>(fma, colmask, rowcheck);
+        case 20: return pick<float, 4, 20>(fma, colmask, rowcheck);
         default: return nullptr;
         }
     }
