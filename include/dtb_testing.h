@@ -31,6 +31,23 @@ extern "C" {
 int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_t cols_per_lane, int32_t waves,
                         int32_t k, int32_t n_xcd, int32_t* out, int32_t max_wg);
 
+#define DTB_TEST_SWEEP_STRIDE (17 + DTB_TEST_MAX_NEIGHBOURS)
+
+/*
+ * Run the tile-serial sweep planner (big tiles of depth D over an interior of
+ * rows x cols, at most max_wg workgroups per big tile).  No HIP call is made.
+ *
+ * Returns the number of records (big tiles x workgroups of the launch), or -1
+ * if no plan exists.  If that number is <= max_records, `out` (max_records *
+ * DTB_TEST_SWEEP_STRIDE int32, caller-owned) receives, per big tile and
+ * launch slot: tile index, workgroups of the launch, ext_r0, ext_c0, own_r0,
+ * own_r1, own_c0, own_c1, computed region (r0, r1, c0, c1), stored region
+ * (r0, r1, c0, c1), n_neighbours, neighbours[DTB_TEST_MAX_NEIGHBOURS].  An
+ * idle slot has own_r0 == own_r1.
+ */
+int32_t dtb_test_sweep(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_t cols_per_lane, int32_t waves,
+                       int32_t k, int32_t D, int32_t max_wg, int32_t n_xcd, int32_t* out, int32_t max_records);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -57,10 +58,15 @@ struct dtb_plan_s {
     uint32_t* d_flags = nullptr;
     int* d_err = nullptr;
     void* xbuf[2] = {nullptr, nullptr};
+    // tile-serial sweep (uses ws as its second buffer)
+    SweepPlan sweep;
+    uint32_t* d_bar = nullptr;
+    int nwg_launch = 0;
 
     ~dtb_plan_s()
     {
         if (ws) (void)hipFree(ws);
+        if (d_bar) (void)hipFree(d_bar);
         if (d_wgs) (void)hipFree(d_wgs);
         if (d_flags) (void)hipFree(d_flags);
         if (d_err) (void)hipFree(d_err);
@@ -109,7 +115,8 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
             const void* f0 = dtb_kernel(dtype, R, fma, false, false, &C, &waves);
             if (!f0) continue;
             Layout L;
-            if (!build_layout(rows, cols, R, C, waves, k, kNumXcd, 0, 0, &L)) continue;
+            if (!build_layout(rows, cols, interior(rows, cols), interior(rows, cols), R, C, waves, k, kNumXcd, 0, 0, &L))
+                continue;
             const bool cm = L.cols.narrow, rc = L.rows.narrow;
             const void* f = dtb_kernel(dtype, R, fma, cm, rc, &C, &waves);
             int occ = 0;
@@ -125,6 +132,68 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
                 *colmask = cm;
                 *rowcheck = rc;
                 found = true;
+            }
+        }
+    }
+    return found;
+}
+
+// Model of one time step of the sweep, in microseconds: every big tile runs
+// D steps on the whole chip (VALU time of one register tile per step), one
+// exchange every k steps, one device-wide barrier, and its HBM traffic (load
+// of the computed region, store of the valid part) once per D steps.
+double sweep_step_us(const SweepPlan& sp, int dtype)
+{
+    const double instr_per_cell = 5.0 + 4.0 / sp.C;
+    const double t_step = (double)sp.ER * sp.EC * instr_per_cell / (64.0 * 2400.0) * 1.5;  // 64 lanes/clk/CU, 2.4 GHz, 1.5x slack
+    const double t_exch = 3.0, t_bar = 5.0;
+    const double hbm_bytes_per_us = 4.0e6;
+    const double b = dtype == DTB_F64 ? 8.0 : 4.0;
+    double total = 0;
+    for (const Layout& L : sp.tiles) {
+        const double cr = (double)(L.rows.bounds.back() - L.rows.bounds.front()) *
+                          (L.cols.bounds.back() - L.cols.bounds.front());
+        const double io = (cr * b + cr * b) / hbm_bytes_per_us;  // upper bound: store <= load
+        total += sp.D * t_step + ((double)sp.D / sp.k) * t_exch + t_bar + io;
+    }
+    return total / sp.D;
+}
+
+bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o, int n_cu, bool fma, SweepPlan* best,
+                  const void** best_func, bool* colmask, bool* rowcheck, int* nwg_cap)
+{
+    double best_t = 1e300;
+    bool found = false;
+    std::vector<int> ks, Ds;
+    if (o.ghost_k > 0) ks.push_back(o.ghost_k);
+    else ks = {4, 6, 8, 10, 12};
+    if (o.depth_D > 0) Ds.push_back(o.depth_D);
+    else Ds = {8, 16, 24, 32, 48, 64, 96, 128, 192};
+    for (int R : kDtbRowsPerLane) {
+        if (o.rows_per_lane > 0 && o.rows_per_lane != R) continue;
+        int C = 0, waves = 0;
+        if (!dtb_sweep_kernel(dtype, R, fma, false, false, &C, &waves)) continue;
+        const bool cm = cols < kWaveSize * C, rc = rows < waves * R;
+        const void* f = dtb_sweep_kernel(dtype, R, fma, cm, rc, &C, &waves);
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) != hipSuccess) continue;
+        int cap = std::min(occ, 1) * n_cu;  // one tile per compute unit: the tiles of a big tile run side by side
+        if (o.max_wg > 0) cap = std::min(cap, o.max_wg);
+        if (cap < 1) continue;
+        for (int k : ks) {
+            for (int D : Ds) {
+                SweepPlan sp;
+                if (!plan_sweep(rows, cols, R, C, waves, k, D, cap, kNumXcd, &sp)) continue;
+                const double t = sweep_step_us(sp, dtype);
+                if (t < best_t) {
+                    best_t = t;
+                    *best = std::move(sp);
+                    *best_func = f;
+                    *colmask = cm;
+                    *rowcheck = rc;
+                    *nwg_cap = cap;
+                    found = true;
+                }
             }
         }
     }
@@ -168,14 +237,40 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
         } else if (path == DTB_PATH_RESIDENT) {
             return DTB_ERR_NOT_CORESIDENT;
         } else {
-            path = DTB_PATH_STEP;  // until the tile-serial sweep takes grids larger than the chip
+            path = DTB_PATH_SWEEP;  // larger than the chip: big tiles one after another
         }
     }
-    if (path == DTB_PATH_SWEEP) return DTB_ERR_UNSUPPORTED;
+    if (path == DTB_PATH_SWEEP) {
+        const void* f = nullptr;
+        bool cm = false, rc = false;
+        int cap = 0;
+        if (!choose_sweep(rows, cols, dtype, o, di.n_cu, p->fma, &p->sweep, &f, &cm, &rc, &cap))
+            return DTB_ERR_NOT_CORESIDENT;
+        p->kfunc = f;
+        p->colmask = cm;
+        p->rowcheck = rc;
+        p->nwg_launch = p->sweep.nwg;
+        p->layout = p->sweep.tiles.front();  // for describe()
+    }
     p->path = path;
 
     if (path == DTB_PATH_STEP) {
         if (hipMalloc(&p->ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+    } else if (path == DTB_PATH_SWEEP) {
+        const size_t n = p->sweep.table.size();
+        const size_t nwg = (size_t)p->nwg_launch;
+        if (hipMalloc(&p->ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_wgs, n * sizeof(WgDesc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_flags, nwg * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_err, sizeof(int)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_bar, sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        for (int i = 0; i < 2; ++i)
+            if (hipMalloc(&p->xbuf[i], bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMemcpy(p->d_wgs, p->sweep.table.data(), n * sizeof(WgDesc), hipMemcpyHostToDevice) != hipSuccess)
+            return DTB_ERR_HIP;
+        if (hipMemset(p->d_flags, 0, nwg * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+        if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
+        if (hipMemset(p->d_bar, 0, sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
     } else {
         const size_t nwg = p->layout.wgs.size();
         if (hipMalloc(&p->d_wgs, nwg * sizeof(WgDesc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
@@ -236,6 +331,52 @@ dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t 
     return DTB_OK;
 }
 
+dtb_status run_sweep(dtb_plan_t p, void* data, const double* coeffs, int64_t T, hipStream_t st)
+{
+    const int rows = (int)p->rows, cols = (int)p->cols;
+    const SweepPlan& sp = p->sweep;
+    // The second buffer needs the grid's halo: the kernel reads it from whichever buffer is current.
+    if (launch_copy_halo(p->dtype, data, p->ws, p->pitch, rows, cols, st) != hipSuccess) return DTB_ERR_HIP;
+    if (launch_reset_counter(p->d_bar, st) != hipSuccess) return DTB_ERR_HIP;
+    ProbDesc P{};
+    P.grid = data;
+    P.xbuf[0] = p->xbuf[0];
+    P.xbuf[1] = p->xbuf[1];
+    P.pitch = p->pitch;
+    P.T = T;
+    P.rows = rows;
+    P.cols = cols;
+    P.k = sp.k;
+    P.wg0 = 0;
+    P.nwg = p->nwg_launch;
+    P.dtype = p->dtype;
+    P.fma = p->fma ? 1 : 0;
+    P.narrow_cols = p->colmask ? 1 : 0;
+    P.narrow_rows = p->rowcheck ? 1 : 0;
+    for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
+    SweepArgs S{};
+    S.bufs[0] = data;
+    S.bufs[1] = p->ws;
+    S.ntiles = (int)sp.tiles.size();
+    S.nwg = p->nwg_launch;
+    S.D = sp.D;
+    const int64_t nrounds = (T + sp.D - 1) / sp.D;
+    if (nrounds > (1 << 30)) return DTB_ERR_UNSUPPORTED;
+    S.nrounds = (int)nrounds;
+    S.bar = p->d_bar;
+    const WgDesc* table = p->d_wgs;
+    uint32_t* flags = p->d_flags;
+    int* err = p->d_err;
+    uint32_t spin = kSpinLimit;
+    void* args[] = {&P, &S, (void*)&table, (void*)&flags, (void*)&err, &spin};
+    const dim3 grid(p->nwg_launch), block(sp.waves * kWaveSize);
+    if (hipLaunchCooperativeKernel(p->kfunc, grid, block, args, 0, st) != hipSuccess) return DTB_ERR_HIP;
+    if (nrounds & 1) {
+        if (launch_copy_interior(p->dtype, p->ws, data, p->pitch, rows, cols, st) != hipSuccess) return DTB_ERR_HIP;
+    }
+    return DTB_OK;
+}
+
 dtb_status run_plan_impl(dtb_plan_t p, const dtb_grid* g, const double* coeffs, int64_t T, void* stream)
 {
     if (!p || !g || !coeffs || !g->data) return DTB_ERR_INVALID_ARG;
@@ -245,6 +386,7 @@ dtb_status run_plan_impl(dtb_plan_t p, const dtb_grid* g, const double* coeffs, 
     hipStream_t st = (hipStream_t)stream;
     if (p->path == DTB_PATH_STEP) return run_step(p, g->data, coeffs, T, st);
     if (p->path == DTB_PATH_RESIDENT) return run_resident(p, g->data, coeffs, T, st);
+    if (p->path == DTB_PATH_SWEEP) return run_sweep(p, g->data, coeffs, T, st);
     return DTB_ERR_UNSUPPORTED;
 }
 
@@ -335,7 +477,8 @@ dtb_status dtb_plan_check(dtb_plan_t p, void* stream)
     if (e == 0) return DTB_OK;
     // A timed-out run leaves the epoch counters out of step: reset them.
     if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
-    if (hipMemset(p->d_flags, 0, p->layout.wgs.size() * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+    const size_t nflags = p->path == DTB_PATH_SWEEP ? (size_t)p->nwg_launch : p->layout.wgs.size();
+    if (hipMemset(p->d_flags, 0, nflags * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
     return DTB_ERR_TIMEOUT;
 }
 
@@ -343,7 +486,9 @@ dtb_status dtb_plan_describe(dtb_plan_t p, int64_t* v, int32_t n)
 {
     if (!p || (n > 0 && !v) || n < 0) return DTB_ERR_INVALID_ARG;
     const Layout& L = p->layout;
-    const int64_t all[] = {p->path, L.nwg, L.k, 0, L.ER, L.EC, L.rows.parts, L.cols.parts, L.R, L.C, 0,
+    const bool sw = p->path == DTB_PATH_SWEEP;
+    const int64_t all[] = {p->path, sw ? p->nwg_launch : L.nwg, L.k, sw ? p->sweep.D : 0, L.ER, L.EC,
+                           L.rows.parts, L.cols.parts, L.R, L.C, sw ? (int64_t)p->sweep.tiles.size() : 0,
                            p->fma ? 0 : 1};
     for (int32_t i = 0; i < n && i < (int32_t)(sizeof(all) / sizeof(all[0])); ++i) v[i] = all[i];
     return DTB_OK;
@@ -395,7 +540,9 @@ int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32
     Layout L;
     if (rows_per_lane < 1 || cols_per_lane < 1 || waves < 1 || k < 1 || max_wg < 0 || (max_wg > 0 && !out))
         return -1;
-    if (!build_layout(rows, cols, rows_per_lane, cols_per_lane, waves, k, n_xcd, 0, 0, &L)) return -1;
+    if (!build_layout(rows, cols, interior(rows, cols), interior(rows, cols), rows_per_lane, cols_per_lane, waves, k,
+                      n_xcd, 0, 0, &L))
+        return -1;
     if (L.nwg > max_wg) return L.nwg;
     for (int i = 0; i < L.nwg; ++i) {
         const WgDesc& d = L.wgs[i];
@@ -411,6 +558,30 @@ int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32
         o[7 + kMaxNeighbours] = (L.rows.narrow ? 1 : 0) | (L.cols.narrow ? 2 : 0);
     }
     return L.nwg;
+}
+
+int32_t dtb_test_sweep(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_t cols_per_lane, int32_t waves,
+                       int32_t k, int32_t D, int32_t max_wg, int32_t n_xcd, int32_t* out, int32_t max_records)
+{
+    if (rows < 1 || cols < 1 || rows_per_lane < 1 || cols_per_lane < 1 || waves < 1 || k < 1 || D < 1 ||
+        max_wg < 1 || max_records < 0 || (max_records > 0 && !out))
+        return -1;
+    SweepPlan sp;
+    if (!plan_sweep(rows, cols, rows_per_lane, cols_per_lane, waves, k, D, max_wg, n_xcd, &sp)) return -1;
+    const int nt = (int)sp.tiles.size();
+    const int64_t nrec = (int64_t)nt * sp.nwg;
+    if (nrec > max_records) return (int32_t)std::min<int64_t>(nrec, INT32_MAX);
+    for (int t = 0; t < nt; ++t) {
+        for (int b = 0; b < sp.nwg; ++b) {
+            const WgDesc& d = sp.table[(size_t)t * sp.nwg + b];
+            int32_t* o = out + ((size_t)t * sp.nwg + b) * DTB_TEST_SWEEP_STRIDE;
+            const int32_t v[] = {t, sp.nwg, d.ext_r0, d.ext_c0, d.own_r0, d.own_r1, d.own_c0, d.own_c1,
+                                 d.cr_r0, d.cr_r1, d.cr_c0, d.cr_c1, d.st_r0, d.st_r1, d.st_c0, d.st_c1, d.nnb};
+            for (int i = 0; i < 17; ++i) o[i] = v[i];
+            for (int j = 0; j < kMaxNeighbours; ++j) o[17 + j] = j < d.nnb ? d.nb[j] : -1;
+        }
+    }
+    return (int32_t)nrec;
 }
 
 }  // extern "C"

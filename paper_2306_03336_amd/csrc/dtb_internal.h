@@ -37,15 +37,22 @@ struct ProbDesc {
 // The extended tile is ER x EC cells (ER = waves * rows per lane, EC = 64 *
 // columns per lane); its cell (0, 0) is storage cell (ext_r0, ext_c0).  The
 // owned cells are [own_r0, own_r1) x [own_c0, own_c1) in storage
-// coordinates; the owned regions of a problem's workgroups tile its interior
-// exactly.  nb[] lists the workgroups (same numbering as the table index)
-// whose owned cells lie within k of this one's, i.e. those it exchanges
-// halos with.
+// coordinates; the owned regions of the workgroups working on one region
+// tile it exactly.  That region (the computed region, cr_*) is the whole
+// interior for a grid held on chip, or one big tile plus its D-deep ring for
+// the tile-serial sweep; ghost cells are only refreshed inside it.  Of the
+// owned cells, those inside st_* are written back (the whole interior, or
+// the big tile's valid part).  nb[] lists the workgroups (same numbering as
+// the launch) whose owned cells lie within k of this one's, i.e. those it
+// exchanges halos with.  An idle workgroup (no owned cells) has own_r0 ==
+// own_r1.
 struct alignas(16) WgDesc {
     int32_t prob;
     int32_t ext_r0, ext_c0;
     int32_t own_r0, own_r1, own_c0, own_c1;
     int32_t nnb;
+    int32_t cr_r0, cr_r1, cr_c0, cr_c1;
+    int32_t st_r0, st_r1, st_c0, st_c1;
     int32_t nb[kMaxNeighbours];
 };
 

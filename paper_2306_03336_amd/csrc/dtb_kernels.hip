@@ -34,6 +34,7 @@
 #include <type_traits>
 
 #include "dtb_internal.h"
+#include "dtb_launch.h"
 
 namespace dtb {
 
@@ -290,12 +291,11 @@ struct Tile {
     }
 
     // Refresh the ghost ring (cells within k of the owned region, inside the
-    // interior, not owned) with device-scope (sc1) loads.
-    __device__ __forceinline__ void load_ghost(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk,
-                                               int rows, int cols)
+    // computed region, not owned) with device-scope (sc1) loads.
+    __device__ __forceinline__ void load_ghost(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk)
     {
-        const int r_lo = max(d.own_r0 - kk, 1), r_hi = min(d.own_r1 + kk, rows + 1);
-        const int c_lo = max(d.own_c0 - kk, 1), c_hi = min(d.own_c1 + kk, cols + 1);
+        const int r_lo = max(d.own_r0 - kk, d.cr_r0), r_hi = min(d.own_r1 + kk, d.cr_r1);
+        const int c_lo = max(d.own_c0 - kk, d.cr_c0), c_hi = min(d.own_c1 + kk, d.cr_c1);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int g = g0 + r;
@@ -313,17 +313,27 @@ struct Tile {
         }
     }
 
-    __device__ __forceinline__ void store_owned(T (&x)[R][C], T* __restrict__ grid, int64_t pitch,
-                                                const WgDesc& d)
+    // Owned cells inside the stored region -> dst.  SC1: device-scope stores
+    // (the next round of the sweep reads them on other XCDs).
+    template <bool SC1>
+    __device__ __forceinline__ void store_owned(T (&x)[R][C], T* __restrict__ dst, int64_t pitch, const WgDesc& d)
     {
+        const int r0 = max(d.own_r0, d.st_r0), r1 = min(d.own_r1, d.st_r1);
+        const int c0 = max(d.own_c0, d.st_c0), c1 = min(d.own_c1, d.st_c1);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int g = g0 + r;
-            if (g < d.own_r0 || g >= d.own_r1) continue;
+            if (g < r0 || g >= r1) continue;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const int col = col0 + c;
-                if (col >= d.own_c0 && col < d.own_c1) grid[(int64_t)g * pitch + col] = x[r][c];
+                if (col >= c0 && col < c1) {
+                    if constexpr (SC1)
+                        __hip_atomic_store(dst + (int64_t)g * pitch + col, x[r][c], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    else
+                        dst[(int64_t)g * pitch + col] = x[r][c];
+                }
             }
         }
     }
@@ -367,20 +377,19 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
 // point (a workgroup barrier), so an odd k never lets two consecutive steps
 // share a parity.
 template <bool HALO_ROWS, typename Tl>
-__device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDesc& d, int me, uint32_t* flags,
-                                           int* err, uint32_t spin_limit)
+__device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDesc& d, int64_t steps, int me,
+                                           uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
+                                           uint32_t spin_limit)
 {
     using T = typename std::remove_reference<decltype(t.a[0][0])>::type;
     constexpr int R = sizeof(t.a) / sizeof(t.a[0]);
     constexpr int C = sizeof(t.a[0]) / sizeof(t.a[0][0]);
-    const int rows = P.rows, cols = P.cols, kk = P.k;
+    const int rows = P.rows, kk = P.k;
     const int64_t pitch = P.pitch;
-    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t epoch = 0;
     int64_t done = 0;
     bool exchanged = false;
-    while (done < P.T) {
-        const int64_t left = P.T - done;
+    while (done < steps) {
+        const int64_t left = steps - done;
         const int nsteps = (int)(left < kk ? left : kk);
         for (int s = 0; s + 1 < nsteps; s += 2) {
             t.template step<HALO_ROWS>(t.a, t.b, 0, rows);
@@ -394,32 +403,37 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
                 for (int c = 0; c < C; ++c) t.a[r][c] = t.b[r][c];
         }
         done += nsteps;
-        if (done < P.T) {
+        if (done < steps) {
             T* xb = (T*)P.xbuf[epoch & 1];
             t.publish(t.a, xb, pitch, d, kk);
             ++epoch;
             exchange_point(flags, me, d, base + epoch, err, spin_limit);
             exchanged = true;
-            t.load_ghost(t.a, xb, pitch, d, kk, rows, cols);
+            t.load_ghost(t.a, xb, pitch, d, kk);
         }
     }
-    // Neighbours read their initial ghost ring from the grid; make sure they all
-    // have before the owned cells are written back in place.
+    // Neighbours read their initial ghost ring from the source grid; when the
+    // result goes back in place, make sure they all have before it is written.
     if (!exchanged) {
         ++epoch;
         exchange_point(flags, me, d, base + epoch, err, spin_limit);
     }
-    t.store_owned(t.a, (T*)P.grid, pitch, d);
 }
 
-template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS>
-__device__ __forceinline__ void run_tile(const ProbDesc& P, const WgDesc& d, int me, uint32_t* flags, int* err,
-                                         uint32_t spin_limit, char* lds)
+// One segment of work for one workgroup: load its extended tile from src,
+// advance it `steps` steps (exchanging every k), store its owned cells inside
+// the stored region to dst.  SWEEP: src/dst are the sweep's HBM buffers, read
+// and written with device-scope accesses (other XCDs wrote / will read them
+// inside the same launch).
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS, bool SWEEP>
+__device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int64_t steps,
+                                            int me, uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
+                                            uint32_t spin_limit, char* lds)
 {
     using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>;
     using G = typename Tl::G;
     Tl t;
-    const T* grid = (const T*)P.grid;
+    const T* grid = src;
     const int64_t pitch = P.pitch;
     const int rows = P.rows, cols = P.cols;
     t.edge = (T*)lds;
@@ -439,7 +453,13 @@ __device__ __forceinline__ void run_tile(const ProbDesc& P, const WgDesc& d, int
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int col = t.col0 + c;
-            const T v = (g <= rows + 1 && col <= cols + 1) ? grid[(int64_t)g * pitch + col] : T(0);
+            T v = T(0);
+            if (g <= rows + 1 && col <= cols + 1) {
+                if constexpr (SWEEP)
+                    v = __hip_atomic_load(grid + (int64_t)g * pitch + col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    v = grid[(int64_t)g * pitch + col];
+            }
             t.a[r][c] = v;
             t.b[r][c] = v;
         }
@@ -480,7 +500,8 @@ __device__ __forceinline__ void run_tile(const ProbDesc& P, const WgDesc& d, int
     t.hbe = hx + (t.lane == 63 ? G::ER : 2 * G::ER);
     t.hbwe = hx + (t.lane == 0 ? 0 : (t.lane == 63 ? G::ER : 2 * G::ER));
 
-    run_epochs<HALO_ROWS>(t, P, d, me, flags, err, spin_limit);
+    run_epochs<HALO_ROWS>(t, P, d, steps, me, flags, base, epoch, err, spin_limit);
+    t.template store_owned<SWEEP>(t.a, dst, pitch, d);
 }
 
 // Does the west or east halo of this tile's rows change from row to row?
@@ -520,10 +541,83 @@ __global__ __launch_bounds__(WAVES * 64) void k_dtb(ProbDesc P, const WgDesc* __
     const int me = blockIdx.x;
     const WgDesc& d = wgs[me];
     char* lds = dtb_lds<T, C, R, WAVES>();
+    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t epoch = 0;
+    T* grid = (T*)P.grid;
     if (halo_varies<T, C, R, WAVES, COLMASK>(P, d))
-        run_tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true>(P, d, me, flags, err, spin_limit, lds);
+        run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false>(P, d, grid, grid, P.T, me, flags, base,
+                                                                          epoch, err, spin_limit, lds);
     else
-        run_tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false>(P, d, me, flags, err, spin_limit, lds);
+        run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false>(P, d, grid, grid, P.T, me, flags, base,
+                                                                           epoch, err, spin_limit, lds);
+}
+
+// Device-wide barrier for the sweep: a counter reset to 0 before the launch;
+// barrier number n (1-based) waits until it reaches n * gridDim.x.  Prior
+// device-scope stores are complete (vmcnt 0) before arriving.  Bounded wait
+// as in exchange_point.
+__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t target, int* err, uint32_t spin_limit)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (!reached(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > spin_limit) {
+                __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
+// The tile-serial sweep (Sections 1, 3.1, 3.3, Figure 1): rounds of D steps;
+// in every round the big tiles run one after another on the whole chip, each
+// reading its computed region (valid part + D ring) from buffer A and writing
+// its valid part to buffer B; a device-wide barrier separates tiles.  Round r
+// reads bufs[r & 1] and writes bufs[(r + 1) & 1]; bufs[0] is the grid.
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
+__global__ __launch_bounds__(WAVES * 64) void k_dtb_sweep(ProbDesc P, SweepArgs S, const WgDesc* __restrict__ table,
+                                                          uint32_t* flags, int* err, uint32_t spin_limit)
+{
+    const int me = blockIdx.x;
+    char* lds = dtb_lds<T, C, R, WAVES>();
+    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t epoch = 0;
+    uint32_t nbar = 0;
+    int64_t done = 0;
+    for (int round = 0; round < S.nrounds; ++round) {
+        const T* A = (const T*)S.bufs[round & 1];
+        T* B = (T*)S.bufs[(round + 1) & 1];
+        const int64_t left = P.T - done;
+        const int64_t steps = left < S.D ? left : S.D;
+        for (int tile = 0; tile < S.ntiles; ++tile) {
+            const WgDesc& d = table[(size_t)tile * S.nwg + me];
+            if (d.own_r0 == d.own_r1) {
+                // Idle for this tile: keep the epoch count in step with the others.
+                const int64_t per = (steps + P.k - 1) / P.k - 1;
+                epoch += per > 0 ? (uint32_t)per : 1u;
+            } else if (halo_varies<T, C, R, WAVES, COLMASK>(P, d)) {
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, true>(P, d, A, B, steps, me, flags, base,
+                                                                                 epoch, err, spin_limit, lds);
+            } else {
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, true>(P, d, A, B, steps, me, flags, base,
+                                                                                  epoch, err, spin_limit, lds);
+            }
+            ++nbar;
+            grid_barrier(S.bar, nbar * gridDim.x, err, spin_limit);
+        }
+        done += steps;
+    }
+}
+
+__global__ void k_reset_counter(uint32_t* bar)
+{
+    if (threadIdx.x == 0) __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Copies the halo ring of src into dst (so a one-step workspace sees the grid's boundary).
@@ -588,19 +682,45 @@ hipError_t launch_copy_halo(int dtype, const void* src, void* dst, int64_t pitch
 // of a row per lane either way), 8 waves per workgroup, R rows per lane.
 constexpr int kDtbWaves = 8;
 
-template <typename T, int C, int R>
+template <typename T, int C, int R, bool SW>
 static const void* pick(bool fma, bool colmask, bool rowcheck)
 {
+#define DTB_K(F, M, W) (SW ? (const void*)&k_dtb_sweep<T, C, R, kDtbWaves, F, M, W> \
+                           : (const void*)&k_dtb<T, C, R, kDtbWaves, F, M, W>)
     const int v = (fma ? 4 : 0) | (colmask ? 2 : 0) | (rowcheck ? 1 : 0);
     switch (v) {
-    case 0: return (const void*)&k_dtb<T, C, R, kDtbWaves, false, false, false>;
-    case 1: return (const void*)&k_dtb<T, C, R, kDtbWaves, false, false, true>;
-    case 2: return (const void*)&k_dtb<T, C, R, kDtbWaves, false, true, false>;
-    case 3: return (const void*)&k_dtb<T, C, R, kDtbWaves, false, true, true>;
-    case 4: return (const void*)&k_dtb<T, C, R, kDtbWaves, true, false, false>;
-    case 5: return (const void*)&k_dtb<T, C, R, kDtbWaves, true, false, true>;
-    case 6: return (const void*)&k_dtb<T, C, R, kDtbWaves, true, true, false>;
-    default: return (const void*)&k_dtb<T, C, R, kDtbWaves, true, true, true>;
+    case 0: return DTB_K(false, false, false);
+    case 1: return DTB_K(false, false, true);
+    case 2: return DTB_K(false, true, false);
+    case 3: return DTB_K(false, true, true);
+    case 4: return DTB_K(true, false, false);
+    case 5: return DTB_K(true, false, true);
+    case 6: return DTB_K(true, true, false);
+    default: return DTB_K(true, true, true);
+    }
+#undef DTB_K
+}
+
+template <bool SW>
+static const void* dtb_kernel_t(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
+{
+    *waves = kDtbWaves;
+    if (dtype == 0) {
+        *C = 2;
+        switch (R) {
+        case 8: return pick<double, 2, 8, SW>(fma, colmask, rowcheck);
+        case 16: return pick<double, 2, 16, SW>(fma, colmask, rowcheck);
+        case 24: return pick<double, 2, 24, SW>(fma, colmask, rowcheck);
+        default: return nullptr;
+        }
+    } else {
+        *C = 4;
+        switch (R) {
+        case 8: return pick<float, 4, 8, SW>(fma, colmask, rowcheck);
+        case 16: return pick<float, 4, 16, SW>(fma, colmask, rowcheck);
+        case 20: return pick<float, 4, 20, SW>(fma, colmask, rowcheck);
+        default: return nullptr;
+        }
     }
 }
 
@@ -608,24 +728,18 @@ static const void* pick(bool fma, bool colmask, bool rowcheck)
 // fills the instance geometry.
 const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
 {
-    *waves = kDtbWaves;
-    if (dtype == 0) {
-        *C = 2;
-        switch (R) {
-        case 8: return pick<double, 2, 8>(fma, colmask, rowcheck);
-        case 16: return pick<double, 2, 16>(fma, colmask, rowcheck);
-        case 24: return pick<double, 2, 24>(fma, colmask, rowcheck);
-        default: return nullptr;
-        }
-    } else {
-        *C = 4;
-        switch (R) {
-        case 8: return pick<float, 4, 8>(fma, colmask, rowcheck);
-        case 16: return pick<float, 4, 16>(fma, colmask, rowcheck);
-        case 20: return pick<float, 4, 20>(fma, colmask, rowcheck);
-        default: return nullptr;
-        }
-    }
+    return dtb_kernel_t<false>(dtype, R, fma, colmask, rowcheck, C, waves);
+}
+
+const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
+{
+    return dtb_kernel_t<true>(dtype, R, fma, colmask, rowcheck, C, waves);
+}
+
+hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, bar);
+    return hipGetLastError();
 }
 
 }  // namespace dtb

@@ -17,4 +17,17 @@ hipError_t launch_copy_halo(int dtype, const void* src, void* dst, int64_t pitch
 // per workgroup of the instance.
 const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves);
 
+// The tile-serial sweep kernel of the same instance (arguments: ProbDesc,
+// SweepArgs, descriptor table, flags, error word, spin limit).
+const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves);
+
+// Arguments of the sweep kernel besides the problem.
+struct SweepArgs {
+    void* bufs[2];   // round r reads bufs[r & 1], writes bufs[(r + 1) & 1]; bufs[0] is the grid
+    int32_t ntiles, nwg, D, nrounds;
+    uint32_t* bar;   // device-wide barrier counter (reset before every launch)
+};
+
+hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st);
+
 }  // namespace dtb

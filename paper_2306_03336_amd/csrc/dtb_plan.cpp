@@ -6,29 +6,42 @@
 
 namespace dtb {
 
-bool split_axis(int64_t len, int ext, int k, int parts, AxisSplit* out)
+int64_t axis_capacity(int ext, int k, int parts)
 {
-    if (len < 1 || ext < 1 || k < 1 || parts < 1 || parts > len) return false;
+    if (parts < 1) return 0;
+    if (parts == 1) return ext;
+    const int64_t inner = ext - 2 * k, edge = ext - k;
+    if (edge < 1) return 0;
+    if (parts > 2 && inner < 1) return 0;
+    return 2 * edge + (int64_t)(parts - 2) * std::max<int64_t>(inner, 0);
+}
+
+bool split_axis(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int parts, AxisSplit* out)
+{
+    const int64_t len = hi - lo;
+    if (len < 1 || lo < 1 || hi > dom + 1 || ext < 1 || k < 1 || parts < 1 || parts > len) return false;
     AxisSplit s;
     s.parts = parts;
     s.bounds.assign(parts + 1, 0);
     s.ext0.assign(parts, 1);
-    if (parts == 1) {
-        if (len > ext) return false;
+    s.narrow = dom < ext;
+    if (s.narrow) {
+        // The whole interior fits in one extended tile placed at its start.
+        if (parts != 1 || lo != 1 || hi != dom + 1) return false;
         s.bounds[0] = 1;
-        s.bounds[1] = (int)len + 1;
+        s.bounds[1] = (int)dom + 1;
         s.ext0[0] = 1;
-        s.narrow = len < ext;
         *out = s;
         return true;
     }
-    if (len < ext) return false;  // several tiles need aligned extended tiles inside the axis
-    // Capacities: an edge tile needs a ghost ring on one side only.
+    // Capacities: an end tile of the range needs a ghost ring on one side only.
     std::vector<int64_t> cap(parts), w(parts, 0);
-    for (int i = 0; i < parts; ++i) cap[i] = (i == 0 || i == parts - 1) ? ext - k : ext - 2 * k;
-    for (int i = 0; i < parts; ++i)
+    for (int i = 0; i < parts; ++i) {
+        const int sides = (parts == 1) ? 0 : ((i == 0 || i == parts - 1) ? 1 : 2);
+        cap[i] = ext - (int64_t)sides * k;
         if (cap[i] < 1) return false;
-    // Even split, then hand the remainder to tiles with room, edges first.
+    }
+    // Even split, then hand the remainder to tiles with room, ends first.
     const int64_t q = len / parts;
     int64_t left = len;
     for (int i = 0; i < parts; ++i) {
@@ -37,7 +50,7 @@ bool split_axis(int64_t len, int ext, int k, int parts, AxisSplit* out)
     }
     std::vector<int> order;
     order.push_back(0);
-    order.push_back(parts - 1);
+    if (parts > 1) order.push_back(parts - 1);
     for (int i = 1; i < parts - 1; ++i) order.push_back(i);
     while (left > 0) {
         bool moved = false;
@@ -51,39 +64,41 @@ bool split_axis(int64_t len, int ext, int k, int parts, AxisSplit* out)
         }
         if (!moved) return false;
     }
-    s.bounds[0] = 1;
+    s.bounds[0] = (int)lo;
     for (int i = 0; i < parts; ++i) s.bounds[i + 1] = s.bounds[i] + (int)w[i];
     for (int i = 0; i < parts; ++i) {
+        if (w[i] < 1) return false;
         const int64_t o0 = s.bounds[i], o1 = s.bounds[i + 1];
-        int64_t e0 = std::min<int64_t>(std::max<int64_t>(o0 - k, 1), len - ext + 1);
-        const int64_t f0 = std::max<int64_t>(o0 - k, 1), f1 = std::min<int64_t>(o1 + k, len + 1);
-        if (f0 < e0 || f1 > e0 + ext || w[i] < 1) return false;
+        const int64_t f0 = std::max<int64_t>(o0 - k, lo), f1 = std::min<int64_t>(o1 + k, hi);
+        const int64_t e0 = std::min<int64_t>(std::max<int64_t>(f0, 1), dom - ext + 1);
+        if (f0 < e0 || f1 > e0 + ext) return false;
         s.ext0[i] = (int)e0;
     }
-    s.narrow = false;
     *out = s;
     return true;
 }
 
-int min_parts(int64_t len, int ext, int k, int max_parts)
+int min_parts(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int max_parts)
 {
-    if (len <= ext) return 1;
-    // Capacity grows linearly in parts: 2(ext-k) + (parts-2)(ext-2k).
-    if (ext - 2 * k < 1) {
-        AxisSplit s;
-        return split_axis(len, ext, k, 2, &s) ? 2 : 0;
-    }
+    const int64_t len = hi - lo;
+    if (len < 1) return 0;
+    AxisSplit s;
+    if (len <= ext && split_axis(lo, hi, dom, ext, k, 1, &s)) return 1;
     int64_t p = 2;
-    if (len > 2 * (int64_t)(ext - k)) p = 2 + (len - 2 * (int64_t)(ext - k) + (ext - 2 * k) - 1) / (ext - 2 * k);
+    const int64_t inner = ext - 2 * k, edge = ext - k;
+    if (edge < 1) return 0;
+    if (len > 2 * edge) {
+        if (inner < 1) return 0;
+        p = 2 + (len - 2 * edge + inner - 1) / inner;
+    }
     for (; p <= max_parts && p <= len; ++p) {
-        AxisSplit s;
-        if (split_axis(len, ext, k, (int)p, &s)) return (int)p;
+        if (split_axis(lo, hi, dom, ext, k, (int)p, &s)) return (int)p;
     }
     return 0;
 }
 
-bool build_layout(int64_t rows, int64_t cols, int R, int C, int waves, int k, int n_xcd, int wg_base,
-                  int prob, Layout* out)
+bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st, int R, int C, int waves, int k,
+                  int n_xcd, int wg_base, int prob, Layout* out)
 {
     Layout L;
     L.R = R;
@@ -92,10 +107,12 @@ bool build_layout(int64_t rows, int64_t cols, int R, int C, int waves, int k, in
     L.ER = waves * R;
     L.EC = kWaveSize * C;
     L.k = k;
-    const int pr = min_parts(rows, L.ER, k, 1 << 20);
-    const int pc = min_parts(cols, L.EC, k, 1 << 20);
+    const int pr = min_parts(cr.r0, cr.r1, rows, L.ER, k, 1 << 20);
+    const int pc = min_parts(cr.c0, cr.c1, cols, L.EC, k, 1 << 20);
     if (pr < 1 || pc < 1) return false;
-    if (!split_axis(rows, L.ER, k, pr, &L.rows) || !split_axis(cols, L.EC, k, pc, &L.cols)) return false;
+    if (!split_axis(cr.r0, cr.r1, rows, L.ER, k, pr, &L.rows) ||
+        !split_axis(cr.c0, cr.c1, cols, L.EC, k, pc, &L.cols))
+        return false;
     const int n = pr * pc;
     L.nwg = n;
 
@@ -109,7 +126,7 @@ bool build_layout(int64_t rows, int64_t cols, int R, int C, int waves, int k, in
             if (n_xcd % a) continue;
             const int b = n_xcd / a;
             if (a > pr || b > pc) continue;
-            const double h = (double)rows / a, w = (double)cols / b;
+            const double h = (double)(cr.r1 - cr.r0) / a, w = (double)(cr.c1 - cr.c0) / b;
             const double score = std::max(h / w, w / h);
             if (score < best) {
                 best = score;
@@ -133,10 +150,8 @@ bool build_layout(int64_t rows, int64_t cols, int R, int C, int waves, int k, in
     std::vector<int> slots(n);
     for (int b = 0; b < n; ++b) slots[b] = b;
     const int nx = std::max(n_xcd, 1);
-    std::stable_sort(slots.begin(), slots.end(), [&](int x, int y) {
-        const int ax = (wg_base + x) % nx, ay = (wg_base + y) % nx;
-        return ax < ay;
-    });
+    std::stable_sort(slots.begin(), slots.end(),
+                     [&](int x, int y) { return (wg_base + x) % nx < (wg_base + y) % nx; });
     std::vector<int> slot_of_tile(n);
     for (int i = 0; i < n; ++i) slot_of_tile[spatial[i]] = slots[i];
 
@@ -151,6 +166,14 @@ bool build_layout(int64_t rows, int64_t cols, int R, int C, int waves, int k, in
             d.own_r1 = L.rows.bounds[tr + 1];
             d.own_c0 = L.cols.bounds[tc];
             d.own_c1 = L.cols.bounds[tc + 1];
+            d.cr_r0 = cr.r0;
+            d.cr_r1 = cr.r1;
+            d.cr_c0 = cr.c0;
+            d.cr_c1 = cr.c1;
+            d.st_r0 = st.r0;
+            d.st_r1 = st.r1;
+            d.st_c0 = st.c0;
+            d.st_c1 = st.c1;
             d.nnb = 0;
         }
     }
@@ -177,6 +200,98 @@ double layout_cost(const Layout& L, int slots_per_cu, int n_cu, double sync_step
     const int per_cu = (L.nwg + n_cu - 1) / n_cu;
     const double cells = (double)per_cu * L.ER * L.EC;
     return cells * (1.0 + sync_steps / L.k);
+}
+
+// Even split of [1, len + 1) into n ranges.
+static std::vector<int> even_bounds(int64_t len, int n)
+{
+    std::vector<int> b(n + 1);
+    for (int i = 0; i <= n; ++i) b[i] = 1 + (int)(len * i / n);
+    return b;
+}
+
+bool plan_sweep(int64_t rows, int64_t cols, int R, int C, int waves, int k, int D, int max_wg, int n_xcd,
+                SweepPlan* out)
+{
+    if (D < 1 || k < 1 || max_wg < 1) return false;
+    const int ER = waves * R, EC = kWaveSize * C;
+    // Pick the workgroup grid pr x pc (pr * pc <= max_wg) whose big tiles
+    // (capacity minus a D ring on each side) need the fewest tiles.
+    int best_nt = 0;
+    double best_score = 1e300;
+    std::vector<int> best_vr, best_vc;
+    for (int pr = 1; pr <= max_wg; ++pr) {
+        const int pc = max_wg / pr;
+        if (pc < 1) break;
+        const int64_t cap_r = axis_capacity(ER, k, pr), cap_c = axis_capacity(EC, k, pc);
+        // An interior big tile has a D ring on both sides.
+        const int64_t lr = std::min<int64_t>(cap_r - 2 * (int64_t)D, rows);
+        const int64_t lc = std::min<int64_t>(cap_c - 2 * (int64_t)D, cols);
+        if (lr < 1 || lc < 1) continue;
+        const int nr = (int)((rows + lr - 1) / lr), nc = (int)((cols + lc - 1) / lc);
+        const double nt = (double)nr * nc;
+        // Tiles processed one after another: time ~ number of tiles; break
+        // ties toward less redundant ring.
+        const double vr = (double)rows / nr, vc = (double)cols / nc;
+        const double redundancy = (vr + 2.0 * D) * (vc + 2.0 * D) / (vr * vc);
+        const double score = nt * 1000.0 + redundancy;
+        if (score < best_score) {
+            best_score = score;
+            best_nt = (int)nt;
+            best_vr = even_bounds(rows, nr);
+            best_vc = even_bounds(cols, nc);
+        }
+    }
+    if (best_nt < 1) return false;
+    SweepPlan P;
+    P.R = R;
+    P.C = C;
+    P.waves = waves;
+    P.ER = ER;
+    P.EC = EC;
+    P.k = k;
+    P.D = D;
+    P.vr = best_vr;
+    P.vc = best_vc;
+    P.tiles_r = (int)best_vr.size() - 1;
+    P.tiles_c = (int)best_vc.size() - 1;
+    P.nwg = 0;
+    for (int i = 0; i < P.tiles_r; ++i) {
+        for (int j = 0; j < P.tiles_c; ++j) {
+            Region st{P.vr[i], P.vr[i + 1], P.vc[j], P.vc[j + 1]};
+            Region cr{std::max(st.r0 - D, 1), std::min<int>(st.r1 + D, (int)rows + 1), std::max(st.c0 - D, 1),
+                      std::min<int>(st.c1 + D, (int)cols + 1)};
+            Layout L;
+            if (!build_layout(rows, cols, cr, st, R, C, waves, k, n_xcd, 0, 0, &L)) return false;
+            if (L.nwg > max_wg) return false;
+            P.nwg = std::max(P.nwg, L.nwg);
+            P.tiles.push_back(std::move(L));
+        }
+    }
+    // Launch table: every big tile gets P.nwg descriptors; missing ones are idle.
+    const int nt = (int)P.tiles.size();
+    P.table.assign((size_t)nt * P.nwg, WgDesc{});
+    for (int t = 0; t < nt; ++t) {
+        const Layout& L = P.tiles[t];
+        for (int b = 0; b < P.nwg; ++b) {
+            WgDesc& d = P.table[(size_t)t * P.nwg + b];
+            if (b < L.nwg) {
+                d = L.wgs[b];
+            } else {
+                d = WgDesc{};
+                d.ext_r0 = 1;
+                d.ext_c0 = 1;
+                d.own_r0 = d.own_r1 = 1;
+                d.own_c0 = d.own_c1 = 1;
+                d.nnb = 0;
+            }
+        }
+    }
+    // Cost per time step: every big tile runs on the whole chip one after another.
+    const double ring = 1.0;  // placeholder weight for per-tile fixed costs
+    P.est_cost = nt * ((double)ER * EC * (1.0 + 1.0 / k) + ring * ER * EC * 8.0 / D);
+    *out = std::move(P);
+    return true;
 }
 
 }  // namespace dtb

@@ -1,9 +1,11 @@
 // dtb_plan.h -- the tile planner (host C++, no HIP calls; testable on a CPU).
 //
-// The whole-GPU tiling of the paper (Abstract, Section 1): the grid is cut
-// into one tile per workgroup such that all tiles together occupy the
-// on-chip storage of the whole device, and every tile carries a ghost ring
-// deep enough for k time steps between exchanges (Section 3.2).
+// The whole-GPU tiling of the paper (Abstract, Section 1): a region of the
+// grid is cut into one tile per workgroup such that all tiles together
+// occupy the on-chip storage of the whole device, and every tile carries a
+// ghost ring deep enough for k time steps between exchanges (Section 3.2).
+// Grids larger than the chip are cut into big tiles processed one after
+// another, several steps each (Section 3.3, Figure 1): the tile-serial sweep.
 #pragma once
 #include <stdint.h>
 
@@ -13,42 +15,81 @@
 
 namespace dtb {
 
+// Storage-coordinate rectangle [r0, r1) x [c0, c1).
+struct Region {
+    int r0 = 0, r1 = 0, c0 = 0, c1 = 0;
+};
+
 // Owned extents along one axis.  bounds has parts + 1 entries (storage
-// coordinates, bounds[0] = 1, bounds[parts] = len + 1); ext0[i] is the storage
+// coordinates, bounds[0] = lo, bounds[parts] = hi); ext0[i] is the storage
 // coordinate of tile i's extended-tile origin.
 struct AxisSplit {
     int parts = 0;
     std::vector<int> bounds;
     std::vector<int> ext0;
-    bool narrow = false;  // the axis is shorter than the extended tile (halo lies inside it)
+    bool narrow = false;  // the interior axis is shorter than the extended tile (the halo lies inside it)
 };
 
-// Split an interior axis of `len` cells into `parts` owned ranges whose
-// k-deep fresh ring fits in an extended tile of `ext` cells.  Returns false
-// if that is impossible.
-bool split_axis(int64_t len, int ext, int k, int parts, AxisSplit* out);
+// Split the range [lo, hi) of an interior axis of `dom` cells (storage
+// coordinates 1..dom) into `parts` owned ranges whose k-deep fresh ring,
+// clipped to [lo, hi), fits in an extended tile of `ext` cells placed inside
+// the interior.  Returns false if that is impossible.
+bool split_axis(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int parts, AxisSplit* out);
 
 // Smallest feasible number of parts (or 0 if none up to max_parts).
-int min_parts(int64_t len, int ext, int k, int max_parts);
+int min_parts(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int max_parts);
+
+// Largest range one axis of `parts` tiles can cover.
+int64_t axis_capacity(int ext, int k, int parts);
 
 struct Layout {
     int R = 0, C = 0, waves = 0, ER = 0, EC = 0, k = 0;
     AxisSplit rows, cols;
     int nwg = 0;
-    std::vector<WgDesc> wgs;  // indexed by blockIdx
+    std::vector<WgDesc> wgs;  // indexed by blockIdx - wg_base
 };
 
-// Build the descriptor table for one problem: tiles in an order that keeps
-// each group of spatially adjacent tiles on one XCD (blockIdx % n_xcd), and
-// for every tile the list of tiles within k of it.  wg_base offsets every
-// workgroup index (for packing several problems into one launch); prob is
-// stored in each descriptor.  Returns false if a neighbour list overflows.
-bool build_layout(int64_t rows, int64_t cols, int R, int C, int waves, int k, int n_xcd, int wg_base,
-                  int prob, Layout* out);
+// Build the descriptor table for the computed region `cr` of a rows x cols
+// interior (cells written back: `st`): tiles in an order that keeps each
+// group of spatially adjacent tiles on one XCD ((wg_base + blockIdx) %
+// n_xcd), and for every tile the list of tiles within k of it.  wg_base
+// offsets every workgroup index (several problems in one launch); prob is
+// stored in each descriptor.  Returns false if no layout exists or a
+// neighbour list overflows.
+bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st, int R, int C, int waves, int k,
+                  int n_xcd, int wg_base, int prob, Layout* out);
+
+// The whole interior as computed and stored region.
+inline Region interior(int64_t rows, int64_t cols) { return Region{1, (int)rows + 1, 1, (int)cols + 1}; }
 
 // Static cost estimate of one step of a layout on a device with `slots`
 // co-resident workgroup slots: cells each compute unit advances per step,
 // times a factor for the exchange every k steps.
 double layout_cost(const Layout& L, int slots_per_cu, int n_cu, double sync_steps);
+
+// ---- tile-serial sweep
+
+struct SweepPlan {
+    int R = 0, C = 0, waves = 0, ER = 0, EC = 0, k = 0, D = 0;
+    int tiles_r = 0, tiles_c = 0;        // big tiles per axis
+    std::vector<int> vr, vc;             // valid (stored) bounds of the big tiles, storage coordinates
+    int nwg = 0;                         // workgroups of the launch (max over big tiles)
+    std::vector<Layout> tiles;           // one layout per big tile, row-major
+    std::vector<WgDesc> table;           // [tile][nwg], idle workgroups padded in
+    double est_cost = 0;                 // model cost per time step (arbitrary units)
+};
+
+// Plan the sweep of a rows x cols interior with big tiles whose computed
+// region (valid part + D ring) fits in max_wg workgroups of the given
+// register-tile instance.  Returns false if none fits.
+bool plan_sweep(int64_t rows, int64_t cols, int R, int C, int waves, int k, int D, int max_wg, int n_xcd,
+                SweepPlan* out);
+
+// Exchange points run_epochs performs for a segment of `steps` steps.
+inline int exchanges_per_segment(int64_t steps, int k)
+{
+    const int64_t n = (steps + k - 1) / k - 1;
+    return n > 0 ? (int)n : 1;
+}
 
 }  // namespace dtb

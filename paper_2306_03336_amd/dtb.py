@@ -52,7 +52,8 @@ class Problem(ctypes.Structure):
 
 # Every symbol include/dtb.h and include/dtb_testing.h declare.
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
-           "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout")
+           "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep")
+TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
 
@@ -88,6 +89,10 @@ def load():
     lib.dtb_test_layout.restype = ctypes.c_int32
     lib.dtb_test_layout.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    lib.dtb_test_sweep.restype = ctypes.c_int32
+    lib.dtb_test_sweep.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     _lib = lib
     return lib
 
@@ -213,3 +218,22 @@ def test_layout(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, wa
                         nb=[x for x in o[7:7 + o[6]]], narrow_rows=bool(o[7 + TEST_MAX_NEIGHBOURS] & 1),
                         narrow_cols=bool(o[7 + TEST_MAX_NEIGHBOURS] & 2)))
     return out
+
+
+def test_sweep(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, waves: int, k: int, D: int,
+               max_wg: int, n_xcd: int = 8):
+    """Sweep planner without a GPU: list of big tiles, each a list of per-slot dicts (or None)."""
+    lib = load()
+    n = lib.dtb_test_sweep(rows, cols, rows_per_lane, cols_per_lane, waves, k, D, max_wg, n_xcd, None, 0)
+    if n < 0:
+        return None
+    buf = (ctypes.c_int32 * (n * TEST_SWEEP_STRIDE))()
+    n2 = lib.dtb_test_sweep(rows, cols, rows_per_lane, cols_per_lane, waves, k, D, max_wg, n_xcd, buf, n)
+    assert n2 == n
+    tiles = {}
+    for i in range(n):
+        o = buf[i * TEST_SWEEP_STRIDE:(i + 1) * TEST_SWEEP_STRIDE]
+        tiles.setdefault(o[0], []).append(dict(
+            nwg=o[1], ext_r0=o[2], ext_c0=o[3], own_r0=o[4], own_r1=o[5], own_c0=o[6], own_c1=o[7],
+            cr=(o[8], o[9], o[10], o[11]), st=(o[12], o[13], o[14], o[15]), nb=[x for x in o[17:17 + o[16]]]))
+    return [tiles[t] for t in sorted(tiles)]

@@ -251,3 +251,95 @@ def test_sine_mode_full_size_closed_form():
         err = np.max(np.abs(got[1:-1, 1:-1] - want[1:-1, 1:-1])) / np.max(np.abs(want[1:-1, 1:-1]))
         print(f"[result] sine mode lambda^T={lam ** T:.6f} rel err {err:.3e}")
         assert err < 1e-11
+
+
+# ----------------------------------------------------------------------------- tile-serial sweep
+
+@pytest.mark.parametrize("case", [
+    # rows, cols, max_wg, k, D, T, R
+    (600, 700, 8, 4, 16, 37, 8),      # several big tiles, T not a multiple of D, odd rounds
+    (600, 700, 8, 3, 10, 40, 8),      # even rounds
+    (1000, 333, 6, 5, 12, 25, 16),
+    (300, 1100, 12, 6, 20, 61, 8),
+    (257, 129, 4, 2, 7, 9, 8),
+    (130, 900, 8, 4, 9, 5, 8),        # T < D: one short round
+], ids=lambda c: "x".join(map(str, c)))
+def test_sweep_exact_bitwise(case):
+    rows, cols, max_wg, k, D, T, R = case
+    rng = np.random.default_rng(rows + 7 * cols + T)
+    coeffs = inputs.dirichlet_weights(rng)
+    u_var = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols)
+    u_const = inputs.uniform_grid(rows, cols, rng, halo=0.375)
+    for u in (u_var, u_const):
+        _say("sweep f64", case)
+        got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_SWEEP, ghost_k=k, depth_D=D, max_wg=max_wg,
+                              rows_per_lane=R, exact=True)
+        assert desc["path"] == dtb.PATH_SWEEP and desc["depth_D"] == D and desc["big_tiles"] >= 2, desc
+        ref = oracle.j2d5pt_f64(u, coeffs, T)
+        assert np.array_equal(got, ref), (case, float(np.max(np.abs(got - ref))))
+
+
+def test_sweep_exact_f32_bitwise():
+    rows, cols, T = 500, 1300, 33
+    rng = np.random.default_rng(77)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(np.float32)
+    _say("sweep f32", rows, cols, T)
+    got, desc = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_SWEEP, ghost_k=4, depth_D=14, max_wg=10,
+                          rows_per_lane=8, exact=True)
+    assert desc["big_tiles"] >= 2
+    assert np.array_equal(got, oracle.j2d5pt_f32(u, coeffs, T))
+
+
+def test_sweep_fma_matches_resident_fma():
+    """Same fused chain per cell whichever way the grid is tiled."""
+    rows, cols, T = 700, 900, 45
+    coeffs = inputs.dirichlet_weights(78)
+    u = inputs.uniform_grid(rows, cols, 79, halo=0.25)
+    _say("sweep vs resident", rows, cols, T)
+    sw, d1 = _run_plan(u, coeffs, T, path=dtb.PATH_SWEEP, ghost_k=4, depth_D=20, max_wg=12, rows_per_lane=8)
+    rs, d2 = _run_plan(u, coeffs, T, path=dtb.PATH_RESIDENT, ghost_k=4, rows_per_lane=8)
+    assert d1["path"] == dtb.PATH_SWEEP and d2["path"] == dtb.PATH_RESIDENT
+    assert np.array_equal(sw, rs)
+
+
+@pytest.mark.slow
+def test_sweep_full_size_8192_T1000():
+    """8192^2 FP64, 1000 steps, halo 1.0: the default plan (tile-serial sweep) against the oracle."""
+    w = inputs.workload("j2d5pt_8192x8192_f64_T1000")
+    u0 = w.grid()
+    _say("full size", w.name)
+    g = _dev(u0)
+    plan = dtb.plan_for(g, w.T)
+    desc = plan.describe()
+    assert desc["path"] == dtb.PATH_SWEEP, desc
+    plan.run(g, w.coeffs, w.T)
+    plan.check()
+    got = g.cpu().numpy()
+    del g
+    ref = oracle.j2d5pt_f64(u0, w.coeffs, w.T)
+    err = oracle.rel_max_err(got, ref)
+    print(f"[result] {w.name} plan={desc} rel max err {err:.3e}")
+    assert err <= TOL_F64
+
+
+@pytest.mark.slow
+def test_sweep_full_size_16384_f32():
+    """16384^2 FP32 in the launch configuration planned for T=2000, run for 200 steps,
+    against the FP64 oracle on the same (float-rounded) input."""
+    w = inputs.workload("j2d5pt_16384x16384_f32_T2000")
+    u0 = w.grid().astype(np.float32)
+    _say("full size", w.name)
+    g = _dev(u0)
+    plan = dtb.plan_for(g, w.T)
+    desc = plan.describe()
+    assert desc["path"] == dtb.PATH_SWEEP, desc
+    T = 200
+    plan.run(g, w.coeffs, T)
+    plan.check()
+    got = g.cpu().numpy()
+    del g
+    ref = oracle.j2d5pt_f64(u0.astype(np.float64), np.array(w.coeffs, dtype=np.float32).astype(np.float64), T)
+    err = oracle.rel_max_err(got, ref)
+    print(f"[result] {w.name} plan={desc} T={T} FP32 rel max err vs FP64 oracle {err:.3e}")
+    assert err <= 1e-5

@@ -78,3 +78,54 @@ def test_xcd_grouping_keeps_exchanges_local():
 
 def test_no_layout_when_ring_too_deep():
     assert dtb.test_layout(4096, 4096, 8, 2, 8, 40) is None
+
+
+# ----------------------------------------------------------------------------- tile-serial sweep
+
+@pytest.mark.parametrize("case", [
+    # rows, cols, R, C, waves, k, D, max_wg
+    (600, 700, 8, 2, 8, 4, 16, 8),
+    (1000, 333, 8, 2, 8, 3, 10, 6),
+    (2048, 2048, 24, 2, 8, 8, 48, 64),
+    (8192, 8192, 24, 2, 8, 8, 64, 256),
+    (16384, 16384, 20, 4, 8, 8, 64, 256),
+    (300, 5000, 16, 4, 8, 6, 20, 12),
+], ids=lambda c: "x".join(map(str, c)))
+def test_sweep_plan_properties(case):
+    rows, cols, R, C, waves, k, D, max_wg = case
+    ER, EC = waves * R, 64 * C
+    tiles = dtb.test_sweep(rows, cols, R, C, waves, k, D, max_wg, 8)
+    assert tiles is not None and len(tiles) >= 1
+    stored = np.zeros((rows + 2, cols + 2), dtype=np.int32)
+    for slots in tiles:
+        nwg = slots[0]["nwg"]
+        assert len(slots) == nwg <= max_wg
+        st = slots[0]["st"]
+        cr = slots[0]["cr"]
+        # the computed region is the valid part grown by D, clipped to the interior
+        assert cr == (max(st[0] - D, 1), min(st[1] + D, rows + 1), max(st[2] - D, 1), min(st[3] + D, cols + 1))
+        stored[st[0]:st[1], st[2]:st[3]] += 1
+        active = [d for d in slots if d["own_r0"] < d["own_r1"]]
+        lay = [dict(d, narrow_rows=rows < ER, narrow_cols=cols < EC) for d in active]
+        # owned regions of the active slots tile the computed region exactly
+        owner = np.full((rows + 2, cols + 2), -1, dtype=np.int64)
+        slot_ids = [i for i, d in enumerate(slots) if d["own_r0"] < d["own_r1"]]
+        for i, d in zip(slot_ids, active):
+            blk = owner[d["own_r0"]:d["own_r1"], d["own_c0"]:d["own_c1"]]
+            assert np.all(blk == -1)
+            blk[...] = i
+            f_r0, f_r1 = max(d["own_r0"] - k, cr[0]), min(d["own_r1"] + k, cr[1])
+            f_c0, f_c1 = max(d["own_c0"] - k, cr[2]), min(d["own_c1"] + k, cr[3])
+            assert d["ext_r0"] <= f_r0 and f_r1 <= d["ext_r0"] + ER
+            assert d["ext_c0"] <= f_c0 and f_c1 <= d["ext_c0"] + EC
+            assert 1 <= d["ext_r0"] and (rows < ER or d["ext_r0"] + ER - 1 <= rows)
+            assert 1 <= d["ext_c0"] and (cols < EC or d["ext_c0"] + EC - 1 <= cols)
+        assert np.all(owner[cr[0]:cr[1], cr[2]:cr[3]] >= 0)
+        assert np.sum(owner >= 0) == (cr[1] - cr[0]) * (cr[3] - cr[2])
+        for i, d in zip(slot_ids, active):
+            f = owner[max(d["own_r0"] - k, cr[0]):min(d["own_r1"] + k, cr[1]),
+                      max(d["own_c0"] - k, cr[2]):min(d["own_c1"] + k, cr[3])]
+            assert sorted(d["nb"]) == sorted(set(np.unique(f).tolist()) - {i})
+    # valid parts partition the interior: every cell written exactly once per round
+    assert np.all(stored[1:rows + 1, 1:cols + 1] == 1)
+    assert stored.sum() == rows * cols
