@@ -364,6 +364,8 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
                 __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
+            // Someone else already gave up: stop waiting so the grid drains quickly.
+            if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -569,6 +571,7 @@ __device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t target, int
                 __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
+            if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
