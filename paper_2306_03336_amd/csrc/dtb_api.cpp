@@ -22,7 +22,7 @@ namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // bounded wait: a few seconds of polling
 constexpr int kNumXcd = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
-constexpr int kDtbRowsPerLane[] = {8, 16, 20, 24};  // instantiated: FP64 8, 16, 24; FP32 8, 16, 20
+constexpr int kDtbRowsPerLane[] = {8, 16, 24, 28};  // instantiated: FP64 8, 16, 24; FP32 8, 16, 24, 28
 
 struct DeviceInfo {
     int device = -1;
@@ -98,6 +98,14 @@ dtb_status check_opts(const dtb_plan_opts* o)
     return DTB_OK;
 }
 
+// A kernel instance whose registers spill to scratch is never chosen.
+bool spills(const void* f)
+{
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, f) != hipSuccess) return true;
+    return a.localSizeBytes > 0;
+}
+
 // Choose (rows per lane, k) for the resident path by the static cost model.
 bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o, int n_cu, bool fma,
                      Layout* best_layout, const void** best_func, bool* colmask, bool* rowcheck)
@@ -119,6 +127,7 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
                 continue;
             const bool cm = L.cols.narrow, rc = L.rows.narrow;
             const void* f = dtb_kernel(dtype, R, fma, cm, rc, &C, &waves);
+            if (spills(f)) continue;
             int occ = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) != hipSuccess) continue;
             int cap = occ * n_cu;
@@ -175,6 +184,7 @@ bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o,
         if (!dtb_sweep_kernel(dtype, R, fma, false, false, &C, &waves)) continue;
         const bool cm = cols < kWaveSize * C, rc = rows < waves * R;
         const void* f = dtb_sweep_kernel(dtype, R, fma, cm, rc, &C, &waves);
+        if (spills(f)) continue;
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) != hipSuccess) continue;
         int cap = std::min(occ, 1) * n_cu;  // one tile per compute unit: the tiles of a big tile run side by side

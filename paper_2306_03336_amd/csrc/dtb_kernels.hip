@@ -721,7 +721,8 @@ static const void* dtb_kernel_t(int dtype, int R, bool fma, bool colmask, bool r
         switch (R) {
         case 8: return pick<float, 4, 8, SW>(fma, colmask, rowcheck);
         case 16: return pick<float, 4, 16, SW>(fma, colmask, rowcheck);
-        case 20: return pick<float, 4, 20, SW>(fma, colmask, rowcheck);
+        case 24: return pick<float, 4, 24, SW>(fma, colmask, rowcheck);
+        case 28: return pick<float, 4, 28, SW>(fma, colmask, rowcheck);
         default: return nullptr;
         }
     }
