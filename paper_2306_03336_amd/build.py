@@ -27,8 +27,11 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 
-SOURCES = [
-    ("dtb_kernels.hip", ["-x", "hip", f"--offload-arch={ARCH}"]),
+_HIP = ["-x", "hip", f"--offload-arch={ARCH}"]
+# Largest translation units first so the parallel build finishes sooner.
+SOURCES = [(f"dtb_inst_{n}.hip", _HIP) for n in ("f32_r28", "f32_r24", "f64_r24", "f32_r16", "f64_r16",
+                                                 "f32_r8", "f64_r8")] + [
+    ("dtb_kernels.hip", _HIP),
     ("dtb_plan.cpp", []),
     ("dtb_api.cpp", ["-D__HIP_PLATFORM_AMD__"]),
 ]
@@ -45,7 +48,8 @@ def _compile(src: str, extra: list) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(*s), SOURCES))
     tmp = LIB_PATH + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]

@@ -1,0 +1,11 @@
+// dtb_inst_f32_r24.hip -- the deep-temporal-blocking kernels for FP32, 4 columns x 24 rows per lane.
+#include "dtb_tile.h"
+
+namespace dtb {
+
+const void* pick_f32_r24(bool sweep, bool fma, bool colmask, bool rowcheck)
+{
+    return pick_instance<float, 4, 24>(sweep, fma, colmask, rowcheck);
+}
+
+}  // namespace dtb

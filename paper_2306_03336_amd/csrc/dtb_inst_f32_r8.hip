@@ -1,0 +1,11 @@
+// dtb_inst_f32_r8.hip -- the deep-temporal-blocking kernels for FP32, 4 columns x 8 rows per lane.
+#include "dtb_tile.h"
+
+namespace dtb {
+
+const void* pick_f32_r8(bool sweep, bool fma, bool colmask, bool rowcheck)
+{
+    return pick_instance<float, 4, 8>(sweep, fma, colmask, rowcheck);
+}
+
+}  // namespace dtb

@@ -1,0 +1,11 @@
+// dtb_inst_f64_r16.hip -- the deep-temporal-blocking kernels for FP64, 2 columns x 16 rows per lane.
+#include "dtb_tile.h"
+
+namespace dtb {
+
+const void* pick_f64_r16(bool sweep, bool fma, bool colmask, bool rowcheck)
+{
+    return pick_instance<double, 2, 16>(sweep, fma, colmask, rowcheck);
+}
+
+}  // namespace dtb

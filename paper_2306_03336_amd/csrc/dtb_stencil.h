@@ -1,0 +1,45 @@
+// dtb_stencil.h -- the j2d5pt update of one cell, shared by the kernels.
+//
+// Listing 1 of Zhang et al., GPGPU '23: w*W + e*E + s*S + c*C + n*N with
+// W = (i, j-1), E = (i, j+1), S = (i-1, j), N = (i+1, j).  FMA = false rounds
+// every product and sums left to right in the printed order W, E, S, C, N;
+// FMA = true runs the same chain as one multiply and four fused
+// multiply-adds.  Everything is built with -ffp-contract=off, so nothing is
+// fused unless written here.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dtb {
+
+template <typename T>
+struct Coef {
+    T c, n, s, e, w;
+};
+
+template <typename T>
+__device__ __forceinline__ Coef<T> load_coef(const double* k)
+{
+    return Coef<T>{(T)k[0], (T)k[1], (T)k[2], (T)k[3], (T)k[4]};
+}
+
+template <bool FMA, typename T>
+__device__ __forceinline__ T j2d5pt(T W, T E, T S, T C, T N, const Coef<T>& k)
+{
+    if constexpr (FMA) {
+        T acc = k.w * W;
+        acc = __builtin_fma(k.e, E, acc);
+        acc = __builtin_fma(k.s, S, acc);
+        acc = __builtin_fma(k.c, C, acc);
+        acc = __builtin_fma(k.n, N, acc);
+        return acc;
+    } else {
+        T acc = k.w * W;
+        acc = acc + k.e * E;
+        acc = acc + k.s * S;
+        acc = acc + k.c * C;
+        acc = acc + k.n * N;
+        return acc;
+    }
+}
+
+}  // namespace dtb

@@ -1,0 +1,571 @@
+// dtb_tile.h -- device templates of the deep-temporal-blocking kernels
+// (register tile, steps, exchange, sweep); instantiated per (precision,
+// rows per lane) in the dtb_inst_*.hip translation units.
+//
+// The update (Listing 1 of Zhang et al., GPGPU '23): every interior cell
+// becomes w*W + e*E + s*S + c*C + n*N of the previous step's values, with
+// W = (i, j-1), E = (i, j+1), S = (i-1, j), N = (i+1, j) (x = column j is the
+// contiguous index, y = row i).  Reads and writes never alias within a step
+// (Jacobi).  The one-cell ring around the interior is a fixed Dirichlet halo.
+//
+// The kernels here:
+//
+//  * k_dtb: deep temporal blocking (Sections 1, 3.1-3.3, Figure 1).  One
+//    persistent cooperative launch runs every time step.  Each workgroup keeps
+//    an extended tile -- its owned cells plus a ghost ring k cells deep -- in
+//    the VGPR file (two register sets, ping-ponged between steps), advances it
+//    k steps without touching HBM, then exchanges the k-deep border strips with
+//    the workgroups around it through global memory and per-workgroup epoch
+//    flags (bulk-synchronous, Section 3.2; a neighbour-wise form of the grid
+//    barrier).  Inside a workgroup the waves are stacked vertically; each step
+//    they swap their top and bottom rows through LDS and meet at one s_barrier.
+//    East/west neighbours across lanes come from DPP wave shifts.
+//
+// Arithmetic: with fma == 0 every product is rounded and the sum is taken
+// left to right in the order W, E, S, C, N (the printed order of Listing 1);
+// with fma == 1 the same chain uses fused multiply-adds.  The library is built
+// with -ffp-contract=off so the compiler never fuses on its own.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "dtb_internal.h"
+#include "dtb_launch.h"
+#include "dtb_stencil.h"
+
+namespace dtb {
+
+// ============================================================================ deep temporal blocking
+
+// DPP wave shifts (GFX9 wave_shr:1 / wave_shl:1) with bound_ctrl: a lane
+// whose source lane does not exist (lane 0 for shr, lane 63 for shl) reads 0.
+template <typename T>
+__device__ __forceinline__ T wave_shr1(T v)
+{
+    return __builtin_amdgcn_update_dpp((T)0, v, 0x138, 0xf, 0xf, true);
+}
+template <typename T>
+__device__ __forceinline__ T wave_shl1(T v)
+{
+    return __builtin_amdgcn_update_dpp((T)0, v, 0x130, 0xf, 0xf, true);
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Wrap-safe "counter a has reached b".
+__device__ __forceinline__ bool reached(uint32_t a, uint32_t b) { return (int32_t)(a - b) >= 0; }
+
+// The update with the west and east products given an addend: lane 0 of a
+// west-edge tile reads W = 0 from the shift and gets the halo product w*hW
+// as the addend of its first product; lane 63 of an east-edge tile likewise
+// gets e*hE.  Everywhere else the addends are 0, so fma(w, W, 0) is just the
+// rounded product and both modes keep their operation order:
+//   FMA:   acc = fma(w, W, bw + be); then e, s, c, n by fused multiply-adds;
+//   exact: acc = fma(w, W, bw); p = fma(e, E, be); acc += p; acc += s*S; acc += c*C; acc += n*N.
+template <bool FMA, bool BW, bool BE, typename T>
+__device__ __forceinline__ T j2d5pt_edge(T W, T E, T S, T C, T N, T bw, T be, T bwe, const Coef<T>& k)
+{
+    if constexpr (FMA) {
+        T acc;
+        if constexpr (BW && BE) acc = __builtin_fma(k.w, W, bwe);
+        else if constexpr (BW) acc = __builtin_fma(k.w, W, bw);
+        else if constexpr (BE) acc = __builtin_fma(k.w, W, be);
+        else acc = k.w * W;
+        acc = __builtin_fma(k.e, E, acc);
+        acc = __builtin_fma(k.s, S, acc);
+        acc = __builtin_fma(k.c, C, acc);
+        acc = __builtin_fma(k.n, N, acc);
+        return acc;
+    } else {
+        T acc;
+        if constexpr (BW) acc = __builtin_fma(k.w, W, bw);
+        else acc = k.w * W;
+        T pe;
+        if constexpr (BE) pe = __builtin_fma(k.e, E, be);
+        else pe = k.e * E;
+        acc = acc + pe;
+        acc = acc + k.s * S;
+        acc = acc + k.c * C;
+        acc = acc + k.n * N;
+        return acc;
+    }
+}
+
+// Geometry of one kernel instance: C columns x R rows per lane, WAVES waves
+// stacked vertically.  Extended tile: (WAVES * R) x (64 * C) cells.
+template <typename T, int C, int R, int WAVES>
+struct Geo {
+    static constexpr int ER = WAVES * R;
+    static constexpr int EC = kWaveSize * C;
+    // LDS: edge rows [parity][slot = wave + 1][top/bottom][64 * C], then per
+    // extended row the west and east halo products (w*hW, e*hE) and a row of
+    // zeros (what every other lane reads on the row-by-row halo path).
+    static constexpr int kEdgeElems = 2 * (WAVES + 2) * 2 * EC;
+    static constexpr int kHaloElems = ER * 3;
+    static constexpr size_t kLdsBytes = (size_t)(kEdgeElems + kHaloElems) * sizeof(T);
+};
+
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
+struct Tile {
+    using G = Geo<T, C, R, WAVES>;
+    static constexpr int ER = G::ER;
+    static constexpr int EC = G::EC;
+
+    T a[R][C];
+    T b[R][C];
+
+    T* edge;         // LDS edge rows
+    const T* hbw;    // LDS, per lane: the west products (lane 0) or zeros
+    const T* hbe;    // LDS, per lane: the east products (lane 63) or zeros
+    const T* hbwe;   // LDS, per lane: lane 0 west, lane 63 east, zeros elsewhere
+    int wave, lane;
+    int g0;          // storage row of this wave's row 0
+    int col0;        // storage column of this lane's slot 0
+    bool colact[C];
+    Coef<T> k;
+    T bw, be, bwe;   // halo addends when they are the same for every row
+
+    __device__ __forceinline__ T* edge_row(int parity, int slot, int bottom)
+    {
+        return edge + ((size_t)((parity * (WAVES + 2) + slot) * 2 + bottom)) * EC;
+    }
+
+    // One time step: src -> dst.  `parity` selects the LDS edge buffer.
+    // HALO_ROWS: the halo addends change from row to row (an edge tile of a
+    // grid whose west/east halo is not constant) and are read from LDS.
+    template <bool HALO_ROWS>
+    __device__ __forceinline__ void step(T (&src)[R][C], T (&dst)[R][C], int parity, int rows)
+    {
+        // Publish this wave's current top and bottom rows for the waves above and below.
+        T* mytop = edge_row(parity, wave + 1, 0) + lane * C;
+        T* mybot = edge_row(parity, wave + 1, 1) + lane * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            mytop[c] = src[0][c];
+            mybot[c] = src[R - 1][c];
+        }
+        __syncthreads();
+        T top[C], bot[C];
+        const T* above = edge_row(parity, wave, 1) + lane * C;      // bottom row of the wave above
+        const T* below = edge_row(parity, wave + 2, 0) + lane * C;  // top row of the wave below
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            top[c] = above[c];
+            bot[c] = below[c];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (ROWCHECK) {
+                const int g = g0 + r;
+                if (g < 1 || g > rows) continue;
+            }
+            T rbw = bw, rbe = be, rbwe = bwe;
+            if constexpr (HALO_ROWS) {
+                rbw = hbw[wave * R + r];
+                rbe = hbe[wave * R + r];
+                rbwe = hbwe[wave * R + r];
+            }
+            const T wlane = wave_shr1(src[r][C - 1]);  // west neighbour of slot 0
+            const T elane = wave_shl1(src[r][0]);      // east neighbour of slot C-1
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T Wv = (c == 0) ? wlane : src[r][c - 1];
+                const T Ev = (c == C - 1) ? elane : src[r][c + 1];
+                const T Sv = (r == 0) ? top[c] : src[r - 1][c];
+                const T Nv = (r == R - 1) ? bot[c] : src[r + 1][c];
+                T v;
+                if (c == 0 && c == C - 1)
+                    v = j2d5pt_edge<FMA, true, true>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+                else if (c == 0)
+                    v = j2d5pt_edge<FMA, true, false>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+                else if (c == C - 1)
+                    v = j2d5pt_edge<FMA, false, true>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+                else
+                    v = j2d5pt_edge<FMA, false, false>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+                if constexpr (COLMASK) v = colact[c] ? v : dst[r][c];
+                dst[r][c] = v;
+            }
+            // The row-by-row halo path is rare (edge tiles with a varying
+            // halo); keep the scheduler from hoisting every row's LDS reads,
+            // which would cost a register pair per row.
+            if constexpr (HALO_ROWS) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    // The owned cells within k of an owned edge: what the neighbours need.
+    // Written with device-scope (sc1) stores, which are coherent across XCDs
+    // without an L2 write-back.
+    __device__ __forceinline__ void publish(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk)
+    {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int g = g0 + r;
+            if (g < d.own_r0 || g >= d.own_r1) continue;
+            const bool row_near = (g < d.own_r0 + kk) || (g >= d.own_r1 - kk);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int col = col0 + c;
+                const bool own = col >= d.own_c0 && col < d.own_c1;
+                const bool near = row_near || col < d.own_c0 + kk || col >= d.own_c1 - kk;
+                if (own && near)
+                    __hip_atomic_store(xb + (int64_t)g * pitch + col, x[r][c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+
+    // Refresh the ghost ring (cells within k of the owned region, inside the
+    // computed region, not owned) with device-scope (sc1) loads.
+    __device__ __forceinline__ void load_ghost(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk)
+    {
+        const int r_lo = max(d.own_r0 - kk, d.cr_r0), r_hi = min(d.own_r1 + kk, d.cr_r1);
+        const int c_lo = max(d.own_c0 - kk, d.cr_c0), c_hi = min(d.own_c1 + kk, d.cr_c1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int g = g0 + r;
+            if (g < r_lo || g >= r_hi) continue;
+            const bool row_own = g >= d.own_r0 && g < d.own_r1;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int col = col0 + c;
+                const bool in_ring = col >= c_lo && col < c_hi;
+                const bool own = row_own && col >= d.own_c0 && col < d.own_c1;
+                if (in_ring && !own)
+                    x[r][c] = __hip_atomic_load(xb + (int64_t)g * pitch + col, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+
+    // Owned cells inside the stored region -> dst.  SC1: device-scope stores
+    // (the next round of the sweep reads them on other XCDs).
+    template <bool SC1>
+    __device__ __forceinline__ void store_owned(T (&x)[R][C], T* __restrict__ dst, int64_t pitch, const WgDesc& d)
+    {
+        const int r0 = max(d.own_r0, d.st_r0), r1 = min(d.own_r1, d.st_r1);
+        const int c0 = max(d.own_c0, d.st_c0), c1 = min(d.own_c1, d.st_c1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int g = g0 + r;
+            if (g < r0 || g >= r1) continue;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int col = col0 + c;
+                if (col >= c0 && col < c1) {
+                    if constexpr (SC1)
+                        __hip_atomic_store(dst + (int64_t)g * pitch + col, x[r][c], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    else
+                        dst[(int64_t)g * pitch + col] = x[r][c];
+                }
+            }
+        }
+    }
+};
+
+// Neighbour-wise bulk-synchronous exchange point.
+//
+// The border strips were written with device-scope atomic stores; waiting for
+// them to complete (vmcnt 0) makes them visible to every XCD, so no L2
+// write-back is needed before this workgroup raises its epoch flag.  The
+// first nnb threads of wave 0 then wait (bounded) until each neighbour's flag
+// has reached the same epoch; the ghost ring is read afterwards with
+// device-scope loads, so no L2 invalidate is needed either.  The inline
+// waits double as compiler barriers (memory clobber).  On timeout the error
+// word is set and the wait is abandoned, so the grid always drains.
+__device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const WgDesc& d, uint32_t target,
+                                               int* err, uint32_t spin_limit)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + me, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)threadIdx.x < d.nnb) {
+        const int nb = d.nb[threadIdx.x];
+        uint32_t spins = 0;
+        while (!reached(__hip_atomic_load(flags + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > spin_limit) {
+                __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            // Someone else already gave up: stop waiting so the grid drains quickly.
+            if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
+// All time steps of one tile, the halo addends either fixed (HALO_ROWS =
+// false) or read per row.  The state is in register set a at every epoch
+// boundary: steps go in pairs a -> b -> a (LDS edge parity 0 then 1); an odd
+// tail step is copied back.  A run of k steps is followed by an exchange
+// point (a workgroup barrier), so an odd k never lets two consecutive steps
+// share a parity.
+template <bool HALO_ROWS, typename Tl>
+__device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDesc& d, int64_t steps, int me,
+                                           uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
+                                           uint32_t spin_limit)
+{
+    using T = typename std::remove_reference<decltype(t.a[0][0])>::type;
+    constexpr int R = sizeof(t.a) / sizeof(t.a[0]);
+    constexpr int C = sizeof(t.a[0]) / sizeof(t.a[0][0]);
+    const int rows = P.rows, kk = P.k;
+    const int64_t pitch = P.pitch;
+    int64_t done = 0;
+    bool exchanged = false;
+    while (done < steps) {
+        const int64_t left = steps - done;
+        const int nsteps = (int)(left < kk ? left : kk);
+        for (int s = 0; s + 1 < nsteps; s += 2) {
+            t.template step<HALO_ROWS>(t.a, t.b, 0, rows);
+            t.template step<HALO_ROWS>(t.b, t.a, 1, rows);
+        }
+        if (nsteps & 1) {
+            t.template step<HALO_ROWS>(t.a, t.b, 0, rows);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < C; ++c) t.a[r][c] = t.b[r][c];
+        }
+        done += nsteps;
+        if (done < steps) {
+            T* xb = (T*)P.xbuf[epoch & 1];
+            t.publish(t.a, xb, pitch, d, kk);
+            ++epoch;
+            exchange_point(flags, me, d, base + epoch, err, spin_limit);
+            exchanged = true;
+            t.load_ghost(t.a, xb, pitch, d, kk);
+        }
+    }
+    // Neighbours read their initial ghost ring from the source grid; when the
+    // result goes back in place, make sure they all have before it is written.
+    if (!exchanged) {
+        ++epoch;
+        exchange_point(flags, me, d, base + epoch, err, spin_limit);
+    }
+}
+
+// One segment of work for one workgroup: load its extended tile from src,
+// advance it `steps` steps (exchanging every k), store its owned cells inside
+// the stored region to dst.  SWEEP: src/dst are the sweep's HBM buffers, read
+// and written with device-scope accesses (other XCDs wrote / will read them
+// inside the same launch).
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS, bool SWEEP>
+__device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int64_t steps,
+                                            int me, uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
+                                            uint32_t spin_limit, char* lds)
+{
+    using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>;
+    using G = typename Tl::G;
+    Tl t;
+    const T* grid = src;
+    const int64_t pitch = P.pitch;
+    const int rows = P.rows, cols = P.cols;
+    t.edge = (T*)lds;
+    T* hx = (T*)lds + G::kEdgeElems;  // [0, ER): w*hW, [ER, 2ER): e*hE, [2ER, 3ER): 0
+    t.wave = uniform(threadIdx.x >> 6);
+    t.lane = threadIdx.x & 63;
+    t.g0 = d.ext_r0 + t.wave * R;
+    t.col0 = d.ext_c0 + t.lane * C;
+    t.k = load_coef<T>(P.coeffs);
+#pragma unroll
+    for (int c = 0; c < C; ++c) t.colact[c] = (t.col0 + c) <= cols;
+
+    // ---- load the extended tile (both register sets) and the fixed boundary values
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int g = t.g0 + r;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int col = t.col0 + c;
+            T v = T(0);
+            if (g <= rows + 1 && col <= cols + 1) {
+                if constexpr (SWEEP)
+                    v = __hip_atomic_load(grid + (int64_t)g * pitch + col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    v = grid[(int64_t)g * pitch + col];
+            }
+            t.a[r][c] = v;
+            t.b[r][c] = v;
+        }
+    }
+    // Rows just above and below the extended tile (the halo rows for edge
+    // tiles, stale ghost values otherwise), both parities.
+    const int gt = d.ext_r0 - 1;
+    const int gb = d.ext_r0 + G::ER;
+    for (int idx = threadIdx.x; idx < G::EC; idx += WAVES * kWaveSize) {
+        const int col = d.ext_c0 + idx;
+        const T vt = (col <= cols + 1) ? grid[(int64_t)gt * pitch + col] : T(0);
+        const T vb = (gb <= rows + 1 && col <= cols + 1) ? grid[(int64_t)gb * pitch + col] : T(0);
+        for (int p = 0; p < 2; ++p) {
+            t.edge_row(p, 0, 1)[idx] = vt;
+            t.edge_row(p, WAVES + 1, 0)[idx] = vb;
+        }
+    }
+    // West/east halo products for the rows of an edge tile (zero elsewhere:
+    // the outermost ghost columns of an interior tile are expendable).
+    const bool west_edge = d.ext_c0 == 1;
+    const bool east_edge = !COLMASK && d.ext_c0 + G::EC - 1 == cols;
+    for (int idx = threadIdx.x; idx < G::ER; idx += WAVES * kWaveSize) {
+        const int g = d.ext_r0 + idx;
+        const bool grow = g >= 1 && g <= rows;
+        hx[idx] = (west_edge && grow) ? t.k.w * grid[(int64_t)g * pitch] : T(0);
+        hx[G::ER + idx] = (east_edge && grow) ? t.k.e * grid[(int64_t)g * pitch + cols + 1] : T(0);
+        hx[2 * G::ER + idx] = T(0);
+    }
+    __syncthreads();
+
+    // With HALO_ROWS == false the products are the same on every row (checked
+    // by the caller) and live in registers.
+    const T zero = T(0);
+    t.bw = t.lane == 0 ? hx[0] : zero;
+    t.be = t.lane == 63 ? hx[G::ER] : zero;
+    t.bwe = t.lane == 0 ? hx[0] : (t.lane == 63 ? hx[G::ER] : zero);
+    t.hbw = hx + (t.lane == 0 ? 0 : 2 * G::ER);
+    t.hbe = hx + (t.lane == 63 ? G::ER : 2 * G::ER);
+    t.hbwe = hx + (t.lane == 0 ? 0 : (t.lane == 63 ? G::ER : 2 * G::ER));
+
+    run_epochs<HALO_ROWS>(t, P, d, steps, me, flags, base, epoch, err, spin_limit);
+    t.template store_owned<SWEEP>(t.a, dst, pitch, d);
+}
+
+// Does the west or east halo of this tile's rows change from row to row?
+// (Only edge tiles look: an interior tile never reads the halo.)
+template <typename T, int C, int R, int WAVES, bool COLMASK>
+__device__ __forceinline__ bool halo_varies(const ProbDesc& P, const WgDesc& d)
+{
+    using G = Geo<T, C, R, WAVES>;
+    const T* grid = (const T*)P.grid;
+    const int rows = P.rows, cols = P.cols;
+    const bool west_edge = d.ext_c0 == 1;
+    const bool east_edge = !COLMASK && d.ext_c0 + G::EC - 1 == cols;
+    bool mine = false;
+    if (west_edge || east_edge) {
+        const int r0 = max(d.ext_r0, 1), r1 = min(d.ext_r0 + G::ER - 1, rows);
+        const T w0 = grid[(int64_t)r0 * P.pitch], e0 = grid[(int64_t)r0 * P.pitch + cols + 1];
+        for (int g = r0 + (int)threadIdx.x; g <= r1; g += WAVES * kWaveSize) {
+            if (west_edge && grid[(int64_t)g * P.pitch] != w0) mine = true;
+            if (east_edge && grid[(int64_t)g * P.pitch + cols + 1] != e0) mine = true;
+        }
+    }
+    return __syncthreads_or(mine);
+}
+
+// LDS for the largest instance a kernel can run.
+template <typename T, int C, int R, int WAVES>
+__device__ __forceinline__ char* dtb_lds()
+{
+    __shared__ __attribute__((aligned(16))) char lds[Geo<T, C, R, WAVES>::kLdsBytes];
+    return lds;
+}
+
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
+__global__ __launch_bounds__(WAVES * 64) void k_dtb(ProbDesc P, const WgDesc* __restrict__ wgs,
+                                                    uint32_t* flags, int* err, uint32_t spin_limit)
+{
+    const int me = blockIdx.x;
+    const WgDesc& d = wgs[me];
+    char* lds = dtb_lds<T, C, R, WAVES>();
+    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t epoch = 0;
+    T* grid = (T*)P.grid;
+    if (halo_varies<T, C, R, WAVES, COLMASK>(P, d))
+        run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false>(P, d, grid, grid, P.T, me, flags, base,
+                                                                          epoch, err, spin_limit, lds);
+    else
+        run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false>(P, d, grid, grid, P.T, me, flags, base,
+                                                                           epoch, err, spin_limit, lds);
+}
+
+// Device-wide barrier for the sweep: a counter reset to 0 before the launch;
+// barrier number n (1-based) waits until it reaches n * gridDim.x.  Prior
+// device-scope stores are complete (vmcnt 0) before arriving.  Bounded wait
+// as in exchange_point.
+__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t target, int* err, uint32_t spin_limit)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (!reached(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > spin_limit) {
+                __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
+// The tile-serial sweep (Sections 1, 3.1, 3.3, Figure 1): rounds of D steps;
+// in every round the big tiles run one after another on the whole chip, each
+// reading its computed region (valid part + D ring) from buffer A and writing
+// its valid part to buffer B; a device-wide barrier separates tiles.  Round r
+// reads bufs[r & 1] and writes bufs[(r + 1) & 1]; bufs[0] is the grid.
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
+__global__ __launch_bounds__(WAVES * 64) void k_dtb_sweep(ProbDesc P, SweepArgs S, const WgDesc* __restrict__ table,
+                                                          uint32_t* flags, int* err, uint32_t spin_limit)
+{
+    const int me = blockIdx.x;
+    char* lds = dtb_lds<T, C, R, WAVES>();
+    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t epoch = 0;
+    uint32_t nbar = 0;
+    int64_t done = 0;
+    for (int round = 0; round < S.nrounds; ++round) {
+        const T* A = (const T*)S.bufs[round & 1];
+        T* B = (T*)S.bufs[(round + 1) & 1];
+        const int64_t left = P.T - done;
+        const int64_t steps = left < S.D ? left : S.D;
+        for (int tile = 0; tile < S.ntiles; ++tile) {
+            const WgDesc& d = table[(size_t)tile * S.nwg + me];
+            if (d.own_r0 == d.own_r1) {
+                // Idle for this tile: keep the epoch count in step with the others.
+                const int64_t per = (steps + P.k - 1) / P.k - 1;
+                epoch += per > 0 ? (uint32_t)per : 1u;
+            } else if (halo_varies<T, C, R, WAVES, COLMASK>(P, d)) {
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, true>(P, d, A, B, steps, me, flags, base,
+                                                                                 epoch, err, spin_limit, lds);
+            } else {
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, true>(P, d, A, B, steps, me, flags, base,
+                                                                                  epoch, err, spin_limit, lds);
+            }
+            ++nbar;
+            grid_barrier(S.bar, nbar * gridDim.x, err, spin_limit);
+        }
+        done += steps;
+    }
+}
+
+
+constexpr int kDtbWaves = 8;
+
+// The 2 x 8 kernels (resident / sweep x fma, colmask, rowcheck) of one
+// (precision, columns per lane, rows per lane) instance.
+template <typename T, int C, int R>
+const void* pick_instance(bool sweep, bool fma, bool colmask, bool rowcheck)
+{
+#define DTB_K(F, M, W) (sweep ? (const void*)&k_dtb_sweep<T, C, R, kDtbWaves, F, M, W> \
+                              : (const void*)&k_dtb<T, C, R, kDtbWaves, F, M, W>)
+    const int v = (fma ? 4 : 0) | (colmask ? 2 : 0) | (rowcheck ? 1 : 0);
+    switch (v) {
+    case 0: return DTB_K(false, false, false);
+    case 1: return DTB_K(false, false, true);
+    case 2: return DTB_K(false, true, false);
+    case 3: return DTB_K(false, true, true);
+    case 4: return DTB_K(true, false, false);
+    case 5: return DTB_K(true, false, true);
+    case 6: return DTB_K(true, true, false);
+    default: return DTB_K(true, true, true);
+    }
+#undef DTB_K
+}
+
+}  // namespace dtb
