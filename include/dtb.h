@@ -134,6 +134,12 @@ dtb_status dtb_run(const dtb_grid* grid, const double coeffs[5], int64_t T, dtb_
 dtb_status dtb_run_batched(const dtb_problem* problems, int32_t count, void* stream);
 
 /*
+ * Wait for `stream` and report an in-kernel failure (DTB_ERR_TIMEOUT)
+ * recorded by any batched launch since the previous check; clears it.
+ */
+dtb_status dtb_batch_check(void* stream);
+
+/*
  * Wait for the plan's last run on `stream` and report an in-kernel failure
  * (DTB_ERR_TIMEOUT) recorded since the previous check; clears it.
  */
@@ -149,7 +155,7 @@ dtb_status dtb_plan_describe(dtb_plan_t plan, int64_t* values, int32_t n);
 /* Release a plan and its workspace (after its work has completed).  NULL is a no-op. */
 void dtb_plan_destroy(dtb_plan_t plan);
 
-/* Drop every cached plan (dtb_run's and dtb_run_batched's). */
+/* Drop every cached plan (dtb_run's and dtb_run_batched's); call when no work is in flight. */
 void dtb_cache_clear(void);
 
 /* A static string naming the status. */

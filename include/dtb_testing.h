@@ -48,6 +48,23 @@ int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32
 int32_t dtb_test_sweep(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_t cols_per_lane, int32_t waves,
                        int32_t k, int32_t D, int32_t max_wg, int32_t n_xcd, int32_t* out, int32_t max_records);
 
+#define DTB_TEST_BATCH_STRIDE 10
+
+/*
+ * Run the batch planner for `count` problems (rows[i] x cols[i], dtype[i],
+ * T[i]) on n_slots workgroup slots with register tiles of r64 / r32 rows per
+ * lane.  No HIP call is made.  Returns the number of jobs (== count), or -1.
+ * `jobs` (count * DTB_TEST_BATCH_STRIDE int32, may be NULL) receives, in
+ * global job order: problem, workgroups, sweep (0/1), ntiles, D, nrounds,
+ * flag_base, table_off, start (model us, rounded), duration (model us).
+ * `slot_lists` (may be NULL; n_slots + 1 offsets followed by the
+ * (job, member) pairs, 2 int32 each; size n_slots + 1 + 2 * total members)
+ * receives every slot's work list.
+ */
+int32_t dtb_test_batch(int32_t count, const int64_t* rows, const int64_t* cols, const int32_t* dtype,
+                       const int64_t* T, int32_t r64, int32_t r32, int32_t n_slots, int32_t* jobs,
+                       int32_t* slot_lists, int32_t slot_lists_len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -412,6 +412,193 @@ struct CacheKey {
 std::mutex g_cache_mu;
 std::map<CacheKey, dtb_plan_t> g_cache;
 
+// ---- dtb_run_batched: planned, allocated and turned into a one-node HIP graph
+// on the first call for a set of shapes/precisions/step counts, replayed after.
+struct BatchEntry {
+    int device = -1;
+    BatchPlan plan;
+    int r64 = 0, r32 = 0;
+    std::vector<ProbDesc> probs;  // templates: everything but grid pointer and coefficients
+    ProbDesc* d_probs = nullptr;
+    JobDesc* d_jobs = nullptr;
+    WgDesc* d_table = nullptr;
+    int* d_wl_off = nullptr;
+    WorkItem* d_wl = nullptr;
+    uint32_t* d_flags = nullptr;
+    int* d_err = nullptr;
+    std::vector<void*> bufs;          // exchange buffers and sweep buffers
+    ProbDesc* h_stage[2] = {nullptr, nullptr};  // pinned staging for the per-call descriptors
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int stage = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool cooperative = false;
+
+    ~BatchEntry()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (int i = 0; i < 2; ++i) {
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+            if (h_stage[i]) (void)hipHostFree(h_stage[i]);
+        }
+        for (void* b : bufs) (void)hipFree(b);
+        void* ds[] = {d_probs, d_jobs, d_table, d_wl_off, d_wl, d_flags, d_err};
+        for (void* d : ds)
+            if (d) (void)hipFree(d);
+    }
+};
+
+std::mutex g_batch_mu;
+std::map<std::vector<int64_t>, BatchEntry*> g_batch_cache;
+
+dtb_status make_batch(const dtb_problem* problems, int32_t count, int device, BatchEntry** out)
+{
+    DeviceInfo di;
+    if (!device_info(&di)) return DTB_ERR_HIP;
+    std::unique_ptr<BatchEntry> b(new BatchEntry());
+    b->device = device;
+    const void* kfn = batched_kernel(&b->r64, &b->r32);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, 8 * kWaveSize, 0) != hipSuccess) return DTB_ERR_HIP;
+    const int nslots = std::min(occ, 1) * di.n_cu;
+    if (nslots < 1) return DTB_ERR_NOT_CORESIDENT;
+    std::vector<BatchSpec> specs(count);
+    for (int i = 0; i < count; ++i) {
+        specs[i].rows = problems[i].grid.rows;
+        specs[i].cols = problems[i].grid.cols;
+        specs[i].pitch = problems[i].grid.pitch;
+        specs[i].T = problems[i].T;
+        specs[i].dtype = problems[i].dtype;
+    }
+    if (!plan_batch(specs, b->r64, b->r32, 8, nslots, &b->plan)) return DTB_ERR_UNSUPPORTED;
+    const BatchPlan& bp = b->plan;
+
+    // Per problem: two exchange buffers; per sweep job: the second grid buffer.
+    b->probs.assign(count, ProbDesc{});
+    std::vector<JobDesc> jobs(bp.jobs.size());
+    for (size_t j = 0; j < bp.jobs.size(); ++j) {
+        const BatchJob& J = bp.jobs[j];
+        const dtb_problem& q = problems[J.prob];
+        const size_t bytes = (size_t)(q.grid.rows + 2) * (size_t)q.grid.pitch * elem_size(q.dtype);
+        ProbDesc& P = b->probs[J.prob];
+        for (int i = 0; i < 2; ++i) {
+            void* x = nullptr;
+            if (hipMalloc(&x, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+            b->bufs.push_back(x);
+            P.xbuf[i] = x;
+        }
+        P.pitch = q.grid.pitch;
+        P.T = q.T;
+        P.rows = (int)q.grid.rows;
+        P.cols = (int)q.grid.cols;
+        P.k = J.k;
+        P.wg0 = J.flag_base;
+        P.nwg = J.g;
+        P.dtype = q.dtype;
+        P.fma = 1;
+        P.narrow_cols = J.narrow_cols ? 1 : 0;
+        P.narrow_rows = J.narrow_rows ? 1 : 0;
+        JobDesc& D = jobs[j];
+        D.prob = J.prob;
+        D.g = J.g;
+        D.flag_base = J.flag_base;
+        D.table_off = J.table_off;
+        D.ntiles = J.ntiles;
+        D.D = J.D;
+        D.nrounds = J.nrounds;
+        D.sweep = J.sweep ? 1 : 0;
+        D.ws = nullptr;
+        if (J.sweep) {
+            if (hipMalloc(&D.ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+            b->bufs.push_back(D.ws);
+        }
+    }
+    std::vector<WorkItem> wl(bp.wl_job.size());
+    for (size_t i = 0; i < wl.size(); ++i) wl[i] = WorkItem{bp.wl_job[i], bp.wl_local[i]};
+    auto up = [](void** dst, const void* src, size_t bytes) -> dtb_status {
+        if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return DTB_ERR_HIP;
+        return DTB_OK;
+    };
+    dtb_status st;
+    if ((st = up((void**)&b->d_probs, b->probs.data(), count * sizeof(ProbDesc))) != DTB_OK) return st;
+    if ((st = up((void**)&b->d_jobs, jobs.data(), jobs.size() * sizeof(JobDesc))) != DTB_OK) return st;
+    if ((st = up((void**)&b->d_table, bp.table.data(), bp.table.size() * sizeof(WgDesc))) != DTB_OK) return st;
+    if ((st = up((void**)&b->d_wl_off, bp.wl_off.data(), bp.wl_off.size() * sizeof(int))) != DTB_OK) return st;
+    if ((st = up((void**)&b->d_wl, wl.data(), wl.size() * sizeof(WorkItem))) != DTB_OK) return st;
+    if (hipMalloc(&b->d_flags, std::max(bp.nflags, 1) * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+    if (hipMemset(b->d_flags, 0, std::max(bp.nflags, 1) * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+    if (hipMalloc(&b->d_err, sizeof(int)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+    if (hipMemset(b->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
+    for (int i = 0; i < 2; ++i) {
+        if (hipHostMalloc((void**)&b->h_stage[i], count * sizeof(ProbDesc), hipHostMallocDefault) != hipSuccess)
+            return DTB_ERR_OUT_OF_MEMORY;
+        if (hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) != hipSuccess) return DTB_ERR_HIP;
+    }
+
+    // One kernel node: the persistent batched kernel over every slot.
+    if (hipGraphCreate(&b->graph, 0) != hipSuccess) return DTB_ERR_HIP;
+    static uint32_t spin = kSpinLimit;
+    void* args[] = {(void*)&b->d_probs, (void*)&b->d_jobs, (void*)&b->d_table, (void*)&b->d_wl_off,
+                    (void*)&b->d_wl, (void*)&b->d_flags, (void*)&b->d_err, (void*)&spin};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(kfn);
+    kp.gridDim = dim3(nslots);
+    kp.blockDim = dim3(8 * kWaveSize);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    if (hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) != hipSuccess) return DTB_ERR_HIP;
+    hipKernelNodeAttrValue v{};
+    v.cooperative = 1;
+    b->cooperative = hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v) == hipSuccess;
+    (void)hipGetLastError();
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) return DTB_ERR_HIP;
+    *out = b.release();
+    return DTB_OK;
+}
+
+dtb_status run_batched_impl(const dtb_problem* problems, int32_t count, hipStream_t st)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DTB_ERR_HIP;
+    std::vector<int64_t> key{dev, count};
+    for (int32_t i = 0; i < count; ++i) {
+        const dtb_problem& q = problems[i];
+        key.insert(key.end(), {q.grid.rows, q.grid.cols, q.grid.pitch, q.dtype, q.T});
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchEntry* b = nullptr;
+    auto it = g_batch_cache.find(key);
+    if (it != g_batch_cache.end()) {
+        b = it->second;
+    } else {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess) return DTB_ERR_HIP;
+        if (cs != hipStreamCaptureStatusNone) return DTB_ERR_NOT_PLANNED;
+        dtb_status rc = make_batch(problems, count, dev, &b);
+        if (rc != DTB_OK) return rc;
+        g_batch_cache[key] = b;
+    }
+    // This call's grid pointers and coefficients into the descriptor table.
+    const int s = b->stage;
+    b->stage ^= 1;
+    if (hipEventSynchronize(b->ev[s]) != hipSuccess) return DTB_ERR_HIP;
+    ProbDesc* h = b->h_stage[s];
+    for (int32_t i = 0; i < count; ++i) {
+        h[i] = b->probs[i];
+        h[i].grid = problems[i].grid.data;
+        for (int c = 0; c < 5; ++c) h[i].coeffs[c] = problems[i].coeffs[c];
+    }
+    if (hipMemcpyAsync(b->d_probs, h, count * sizeof(ProbDesc), hipMemcpyHostToDevice, st) != hipSuccess)
+        return DTB_ERR_HIP;
+    if (hipEventRecord(b->ev[s], st) != hipSuccess) return DTB_ERR_HIP;
+    if (hipGraphLaunch(b->exec, st) != hipSuccess) return DTB_ERR_HIP;
+    return DTB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -469,12 +656,26 @@ dtb_status dtb_run_batched(const dtb_problem* problems, int32_t count, void* str
         dtb_status st = check_shape(q.grid.rows, q.grid.cols, q.grid.pitch, q.dtype);
         if (st != DTB_OK) return st;
     }
-    for (int32_t i = 0; i < count; ++i) {
-        const dtb_problem& q = problems[i];
-        dtb_status st = dtb_run(&q.grid, q.coeffs, q.T, (dtb_dtype)q.dtype, stream);
-        if (st != DTB_OK) return st;
+    if (count == 0) return DTB_OK;
+    return run_batched_impl(problems, count, (hipStream_t)stream);
+}
+
+dtb_status dtb_batch_check(void* stream)
+{
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return DTB_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    dtb_status rc = DTB_OK;
+    for (auto& kv : g_batch_cache) {
+        BatchEntry* b = kv.second;
+        int e = 0;
+        if (hipMemcpy(&e, b->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return DTB_ERR_HIP;
+        if (e != 0) {
+            rc = DTB_ERR_TIMEOUT;
+            if (hipMemset(b->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
+            if (hipMemset(b->d_flags, 0, (size_t)b->plan.nflags * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+        }
     }
-    return DTB_OK;
+    return rc;
 }
 
 dtb_status dtb_plan_check(dtb_plan_t p, void* stream)
@@ -521,9 +722,14 @@ void dtb_plan_destroy(dtb_plan_t plan)
 
 void dtb_cache_clear(void)
 {
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    for (auto& kv : g_cache) delete kv.second;
-    g_cache.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (auto& kv : g_cache) delete kv.second;
+        g_cache.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto& kv : g_batch_cache) delete kv.second;
+    g_batch_cache.clear();
 }
 
 const char* dtb_status_string(dtb_status s)
@@ -568,6 +774,42 @@ int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32
         o[7 + kMaxNeighbours] = (L.rows.narrow ? 1 : 0) | (L.cols.narrow ? 2 : 0);
     }
     return L.nwg;
+}
+
+int32_t dtb_test_batch(int32_t count, const int64_t* rows, const int64_t* cols, const int32_t* dtype,
+                       const int64_t* T, int32_t r64, int32_t r32, int32_t n_slots, int32_t* jobs,
+                       int32_t* slot_lists, int32_t slot_lists_len)
+{
+    if (count < 1 || !rows || !cols || !dtype || !T || r64 < 1 || r32 < 1 || n_slots < 1) return -1;
+    std::vector<BatchSpec> specs(count);
+    for (int i = 0; i < count; ++i) {
+        if (rows[i] < 1 || cols[i] < 1 || T[i] < 0 || (dtype[i] != 0 && dtype[i] != 1)) return -1;
+        specs[i].rows = rows[i];
+        specs[i].cols = cols[i];
+        specs[i].pitch = cols[i] + 2;
+        specs[i].T = T[i];
+        specs[i].dtype = dtype[i];
+    }
+    BatchPlan bp;
+    if (!plan_batch(specs, r64, r32, 8, n_slots, &bp)) return -1;
+    if (jobs) {
+        for (size_t j = 0; j < bp.jobs.size(); ++j) {
+            const BatchJob& J = bp.jobs[j];
+            const int32_t v[DTB_TEST_BATCH_STRIDE] = {J.prob, J.g, J.sweep ? 1 : 0, J.ntiles, J.D, J.nrounds,
+                                                      J.flag_base, J.table_off, (int32_t)J.start, (int32_t)J.dur};
+            for (int i = 0; i < DTB_TEST_BATCH_STRIDE; ++i) jobs[j * DTB_TEST_BATCH_STRIDE + i] = v[i];
+        }
+    }
+    if (slot_lists) {
+        const int64_t need = (int64_t)n_slots + 1 + 2 * (int64_t)bp.wl_job.size();
+        if (need > slot_lists_len) return -1;
+        for (int i = 0; i <= n_slots; ++i) slot_lists[i] = bp.wl_off[i];
+        for (size_t i = 0; i < bp.wl_job.size(); ++i) {
+            slot_lists[n_slots + 1 + 2 * i] = bp.wl_job[i];
+            slot_lists[n_slots + 1 + 2 * i + 1] = bp.wl_local[i];
+        }
+    }
+    return (int32_t)bp.jobs.size();
 }
 
 int32_t dtb_test_sweep(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_t cols_per_lane, int32_t waves,

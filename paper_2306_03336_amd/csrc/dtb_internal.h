@@ -56,4 +56,24 @@ struct alignas(16) WgDesc {
     int32_t nb[kMaxNeighbours];
 };
 
+// One job of a batched launch: a problem run by a group of g workgroups,
+// held on chip for all its steps (ntiles = nrounds = 1, D = T, in place) or
+// swept through big tiles with `ws` as the second buffer.
+struct JobDesc {
+    int32_t prob;
+    int32_t g;          // workgroups in the group
+    int32_t flag_base;  // flags[flag_base + i] belong to group member i
+    int32_t table_off;  // descriptors: table[table_off + tile * g + i]
+    int32_t ntiles;
+    int32_t D;
+    int32_t nrounds;
+    int32_t sweep;
+    void* ws;
+};
+
+// Entry of a launch slot's work list: job index and the slot's member index in it.
+struct WorkItem {
+    int32_t job, local;
+};
+
 }  // namespace dtb

@@ -30,4 +30,9 @@ struct SweepArgs {
 
 hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st);
 
+// The batched persistent kernel (arguments: ProbDesc*, JobDesc*, WgDesc*
+// table, work-list offsets, work items, flags, error word, spin limit); the
+// rows per lane it uses for each precision.
+const void* batched_kernel(int* rows_per_lane_f64, int* rows_per_lane_f32);
+
 }  // namespace dtb

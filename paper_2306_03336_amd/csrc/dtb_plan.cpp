@@ -2,6 +2,7 @@
 #include "dtb_plan.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 namespace dtb {
@@ -291,6 +292,136 @@ bool plan_sweep(int64_t rows, int64_t cols, int R, int C, int waves, int k, int 
     const double ring = 1.0;  // placeholder weight for per-tile fixed costs
     P.est_cost = nt * ((double)ER * EC * (1.0 + 1.0 / k) + ring * ER * EC * 8.0 / D);
     *out = std::move(P);
+    return true;
+}
+
+double tile_step_us(int ER, int EC, int C, int active_rows)
+{
+    const double rows = std::min(ER, std::max(active_rows, 1));
+    const double instr_per_cell = 5.0 + 4.0 / C;
+    // 64 FP64/FP32 lanes per clock per CU at 2.4 GHz, with 1.5x slack for
+    // the barrier and LDS traffic of each step, plus a fixed 0.3 us.
+    return rows * EC * instr_per_cell / (64.0 * 2400.0) * 1.5 + 0.3;
+}
+
+bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves, int nslots, BatchPlan* out)
+{
+    if (nslots < 1 || waves < 1) return false;
+    BatchPlan bp;
+    bp.nslots = nslots;
+    const double t_exch = 3.0, t_bar = 5.0;
+    std::vector<BatchJob> jobs;
+    std::vector<std::vector<WgDesc>> tables;
+    int flag_base = 0;
+    for (int p = 0; p < (int)probs.size(); ++p) {
+        const BatchSpec& q = probs[p];
+        const int R = q.dtype == 0 ? r64 : r32, C = q.dtype == 0 ? 2 : 4;
+        const int ER = waves * R, EC = kWaveSize * C;
+        BatchJob J;
+        J.prob = p;
+        J.narrow_cols = q.cols < EC;
+        J.narrow_rows = q.rows < ER;
+        std::vector<WgDesc> tab;
+        bool ok = false;
+        for (int k : {8, 6, 4, 2, 1}) {
+            Layout L;
+            if (build_layout(q.rows, q.cols, interior(q.rows, q.cols), interior(q.rows, q.cols), R, C, waves, k, 1,
+                             flag_base, 0, &L) &&
+                L.nwg <= nslots) {
+                J.sweep = false;
+                J.g = L.nwg;
+                J.k = k;
+                J.D = (int)std::min<int64_t>(q.T, INT32_MAX);
+                const int act = (int)std::min<int64_t>(q.rows, ER);
+                J.dur = q.T * tile_step_us(ER, EC, C, act) + (double)q.T / k * t_exch;
+                tab = L.wgs;
+                ok = true;
+                break;
+            }
+        }
+        if (!ok) {
+            double best = 1e300;
+            for (int k : {8, 4}) {
+                for (int D : {16, 32, 64, 128}) {
+                    SweepPlan sp;
+                    if (!plan_sweep(q.rows, q.cols, R, C, waves, k, D, nslots, 1, &sp)) continue;
+                    const int64_t nrounds = (q.T + D - 1) / D;
+                    const double per_tile = D * tile_step_us(ER, EC, C, ER) + (double)D / k * t_exch + t_bar;
+                    const double dur = nrounds * per_tile * sp.tiles.size();
+                    if (dur < best) {
+                        best = dur;
+                        J.sweep = true;
+                        J.g = sp.nwg;
+                        J.k = k;
+                        J.D = D;
+                        J.ntiles = (int)sp.tiles.size();
+                        J.nrounds = (int)nrounds;
+                        J.dur = dur;
+                        tab = sp.table;
+                        ok = true;
+                    }
+                }
+            }
+            if (ok) {
+                for (WgDesc& d : tab) {
+                    for (int i = 0; i < d.nnb; ++i) d.nb[i] += flag_base;
+                    d.prob = p;
+                }
+            }
+        }
+        if (!ok) return false;
+        J.flag_base = flag_base;
+        flag_base += J.g;
+        jobs.push_back(std::move(J));
+        tables.push_back(std::move(tab));
+    }
+    bp.nflags = flag_base;
+
+    // Longest first onto the slots that free up earliest.
+    std::vector<int> order(jobs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].dur > jobs[b].dur; });
+    std::vector<double> free_at(nslots, 0.0);
+    for (int j : order) {
+        BatchJob& J = jobs[j];
+        std::vector<int> idx(nslots);
+        for (int s = 0; s < nslots; ++s) idx[s] = s;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return free_at[a] < free_at[b]; });
+        J.slots.assign(idx.begin(), idx.begin() + J.g);
+        std::sort(J.slots.begin(), J.slots.end());
+        double start = 0;
+        for (int s : J.slots) start = std::max(start, free_at[s]);
+        J.start = start;
+        for (int s : J.slots) free_at[s] = start + J.dur;
+        bp.makespan = std::max(bp.makespan, start + J.dur);
+    }
+    // Global order: by start time, ties by problem index.
+    std::vector<int> glob(jobs.size());
+    for (size_t i = 0; i < glob.size(); ++i) glob[i] = (int)i;
+    std::stable_sort(glob.begin(), glob.end(), [&](int a, int b) {
+        return jobs[a].start < jobs[b].start || (jobs[a].start == jobs[b].start && a < b);
+    });
+    for (int j : glob) {
+        BatchJob J = jobs[j];
+        J.table_off = (int)bp.table.size();
+        bp.table.insert(bp.table.end(), tables[j].begin(), tables[j].end());
+        bp.jobs.push_back(std::move(J));
+    }
+    // Work lists.
+    std::vector<std::vector<std::pair<int, int>>> lists(nslots);
+    for (int jj = 0; jj < (int)bp.jobs.size(); ++jj) {
+        const BatchJob& J = bp.jobs[jj];
+        for (int i = 0; i < J.g; ++i) lists[J.slots[i]].push_back({jj, i});
+    }
+    bp.wl_off.assign(nslots + 1, 0);
+    for (int s = 0; s < nslots; ++s) {
+        bp.wl_off[s + 1] = bp.wl_off[s] + (int)lists[s].size();
+        for (auto& it : lists[s]) {
+            bp.wl_job.push_back(it.first);
+            bp.wl_local.push_back(it.second);
+        }
+    }
+    *out = std::move(bp);
     return true;
 }
 

@@ -85,6 +85,45 @@ struct SweepPlan {
 bool plan_sweep(int64_t rows, int64_t cols, int R, int C, int waves, int k, int D, int max_wg, int n_xcd,
                 SweepPlan* out);
 
+// ---- batched launch
+
+struct BatchSpec {
+    int64_t rows = 0, cols = 0, pitch = 0, T = 0;
+    int dtype = 0;
+};
+
+struct BatchJob {
+    int prob = 0;
+    bool sweep = false;
+    int g = 0;                 // workgroups of the group
+    int k = 0, D = 0, ntiles = 1, nrounds = 1;
+    int flag_base = 0, table_off = 0;
+    std::vector<int> slots;    // launch slot of each member
+    double start = 0, dur = 0; // model time (us)
+    bool narrow_cols = false, narrow_rows = false;
+};
+
+struct BatchPlan {
+    std::vector<BatchJob> jobs;       // in global order (by start time)
+    std::vector<WgDesc> table;        // all jobs' descriptors
+    std::vector<int> wl_off;          // nslots + 1 offsets into wl
+    std::vector<int> wl_job, wl_local;
+    int nslots = 0, nflags = 0;
+    double makespan = 0;              // model time (us)
+};
+
+// Model time (us) of one step of a register tile of ER x EC cells of which
+// `active_rows` rows hold grid rows.
+double tile_step_us(int ER, int EC, int C, int active_rows);
+
+// Plan a batch: every problem becomes a job on a group of workgroups (held
+// on chip if it fits nslots tiles, else swept through big tiles), the jobs
+// are list-scheduled longest first onto nslots launch slots, and every slot
+// gets its (job, member) work list in one global job order.  FP64 problems
+// use 2 x r64 cells per lane, FP32 4 x r32.  Returns false if a problem fits
+// no layout.
+bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves, int nslots, BatchPlan* out);
+
 // Exchange points run_epochs performs for a segment of `steps` steps.
 inline int exchanges_per_segment(int64_t steps, int k)
 {

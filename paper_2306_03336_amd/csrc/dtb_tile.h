@@ -547,6 +547,138 @@ __global__ __launch_bounds__(WAVES * 64) void k_dtb_sweep(ProbDesc P, SweepArgs 
 
 constexpr int kDtbWaves = 8;
 
+// ============================================================================ batched launch
+
+// Group-wide synchronisation point of a batched job: raise this member's
+// flag, wait (bounded) until every member's flag reached `target`.
+__device__ __forceinline__ void group_point(uint32_t* flags, int flag_base, int g, int local, uint32_t target,
+                                            int* err, uint32_t spin_limit)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(flags + flag_base + local, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = threadIdx.x; i < g; i += blockDim.x) {
+        uint32_t spins = 0;
+        while (!reached(__hip_atomic_load(flags + flag_base + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                        target)) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > spin_limit) {
+                __hip_atomic_fetch_or(err, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
+// One job for one member of its group.  A grid held on chip runs in place
+// (one segment of T steps); a larger one is swept through big tiles, with
+// the halo ring first copied into the second buffer and, after an odd number
+// of rounds, the interior copied back -- both split over the group.
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK>
+__device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, const WgDesc* __restrict__ table,
+                                        int local, uint32_t* flags, int* err, uint32_t spin_limit, char* lds)
+{
+    const int me = J.flag_base + local;
+    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t epoch = 0;
+    T* grid = (T*)P.grid;
+    if (!J.sweep) {
+        const WgDesc& d = table[J.table_off + local];
+        if (halo_varies<T, C, R, WAVES, COLMASK>(P, d))
+            run_segment<T, C, R, WAVES, FMA, COLMASK, true, true, false>(P, d, grid, grid, P.T, me, flags, base,
+                                                                          epoch, err, spin_limit, lds);
+        else
+            run_segment<T, C, R, WAVES, FMA, COLMASK, true, false, false>(P, d, grid, grid, P.T, me, flags, base,
+                                                                           epoch, err, spin_limit, lds);
+        return;
+    }
+    T* ws = (T*)J.ws;
+    const int rows = P.rows, cols = P.cols;
+    const int64_t pitch = P.pitch;
+    const int nthr = J.g * WAVES * kWaveSize;
+    const int tid = local * WAVES * kWaveSize + threadIdx.x;
+    // Halo ring of the grid into the second buffer.
+    for (int idx = tid; idx < 2 * (cols + 2) + 2 * rows; idx += nthr) {
+        int64_t off;
+        if (idx < cols + 2) off = idx;
+        else if (idx < 2 * (cols + 2)) off = (int64_t)(rows + 1) * pitch + (idx - (cols + 2));
+        else {
+            const int j = idx - 2 * (cols + 2);
+            off = (int64_t)(1 + (j >> 1)) * pitch + ((j & 1) ? cols + 1 : 0);
+        }
+        __hip_atomic_store(ws + off, grid[off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    ++epoch;
+    group_point(flags, J.flag_base, J.g, local, base + epoch, err, spin_limit);
+    int64_t done = 0;
+    for (int round = 0; round < J.nrounds; ++round) {
+        const T* A = (round & 1) ? ws : grid;
+        T* B = (round & 1) ? grid : ws;
+        const int64_t left = P.T - done;
+        const int64_t steps = left < J.D ? left : J.D;
+        for (int tile = 0; tile < J.ntiles; ++tile) {
+            const WgDesc& d = table[J.table_off + (size_t)tile * J.g + local];
+            if (d.own_r0 == d.own_r1) {
+                const int64_t per = (steps + P.k - 1) / P.k - 1;
+                epoch += per > 0 ? (uint32_t)per : 1u;
+            } else if (halo_varies<T, C, R, WAVES, COLMASK>(P, d)) {
+                run_segment<T, C, R, WAVES, FMA, COLMASK, true, true, true>(P, d, A, B, steps, me, flags, base,
+                                                                             epoch, err, spin_limit, lds);
+            } else {
+                run_segment<T, C, R, WAVES, FMA, COLMASK, true, false, true>(P, d, A, B, steps, me, flags, base,
+                                                                              epoch, err, spin_limit, lds);
+            }
+            ++epoch;
+            group_point(flags, J.flag_base, J.g, local, base + epoch, err, spin_limit);
+        }
+        done += steps;
+    }
+    if (J.nrounds & 1) {
+        // The result is in the second buffer: copy the interior back.
+        const int64_t n = (int64_t)rows * cols;
+        for (int64_t idx = tid; idx < n; idx += nthr) {
+            const int64_t i = 1 + idx / cols, j = 1 + idx % cols;
+            grid[i * pitch + j] = __hip_atomic_load(ws + i * pitch + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Many grids of uneven sizes, step counts and precisions in one persistent
+// launch.  Launch slot b works through its list of (job, member) items in the
+// global job order the planner chose (so no two jobs can wait on each other).
+// FP64 runs with 2 columns x R64 rows per lane, FP32 with 4 x R32; rows
+// are always checked against the grid (small grids leave rows idle).
+template <int R64, int R32, bool FMA>
+__global__ __launch_bounds__(kDtbWaves * 64) void k_dtb_batched(const ProbDesc* __restrict__ probs,
+                                                                const JobDesc* __restrict__ jobs,
+                                                                const WgDesc* __restrict__ table,
+                                                                const int* __restrict__ wl_off,
+                                                                const WorkItem* __restrict__ wl, uint32_t* flags,
+                                                                int* err, uint32_t spin_limit)
+{
+    constexpr size_t b64 = Geo<double, 2, R64, kDtbWaves>::kLdsBytes;
+    constexpr size_t b32 = Geo<float, 4, R32, kDtbWaves>::kLdsBytes;
+    __shared__ __attribute__((aligned(16))) char lds[b64 > b32 ? b64 : b32];
+    const int slot = blockIdx.x;
+    for (int i = wl_off[slot]; i < wl_off[slot + 1]; ++i) {
+        const WorkItem w = wl[i];
+        const JobDesc& J = jobs[w.job];
+        const ProbDesc& P = probs[J.prob];
+        if (P.dtype == 0) {
+            if (P.narrow_cols) run_job<double, 2, R64, kDtbWaves, FMA, true>(P, J, table, w.local, flags, err, spin_limit, lds);
+            else run_job<double, 2, R64, kDtbWaves, FMA, false>(P, J, table, w.local, flags, err, spin_limit, lds);
+        } else {
+            if (P.narrow_cols) run_job<float, 4, R32, kDtbWaves, FMA, true>(P, J, table, w.local, flags, err, spin_limit, lds);
+            else run_job<float, 4, R32, kDtbWaves, FMA, false>(P, J, table, w.local, flags, err, spin_limit, lds);
+        }
+        __syncthreads();
+    }
+}
+
 // The 2 x 8 kernels (resident / sweep x fma, colmask, rowcheck) of one
 // (precision, columns per lane, rows per lane) instance.
 template <typename T, int C, int R>

@@ -52,7 +52,8 @@ class Problem(ctypes.Structure):
 
 # Every symbol include/dtb.h and include/dtb_testing.h declare.
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
-           "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep")
+           "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep",
+           "dtb_batch_check", "dtb_test_batch")
 TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
@@ -89,6 +90,12 @@ def load():
     lib.dtb_test_layout.restype = ctypes.c_int32
     lib.dtb_test_layout.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    lib.dtb_batch_check.restype = ctypes.c_int
+    lib.dtb_batch_check.argtypes = [P]
+    I64P, I32P = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+    lib.dtb_test_batch.restype = ctypes.c_int32
+    lib.dtb_test_batch.argtypes = [ctypes.c_int32, I64P, I64P, I32P, I64P, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, I32P, I32P, ctypes.c_int32]
     lib.dtb_test_sweep.restype = ctypes.c_int32
     lib.dtb_test_sweep.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -200,6 +207,11 @@ def run_batched(problems, stream=None):
     _check(load().dtb_run_batched(arr, len(problems), _stream(stream)), "dtb_run_batched")
 
 
+def batch_check(stream=None):
+    """dtb_batch_check: wait for the stream, raise if a batched launch recorded a failure."""
+    _check(load().dtb_batch_check(_stream(stream)), "dtb_batch_check")
+
+
 def cache_clear():
     load().dtb_cache_clear()
 
@@ -237,3 +249,26 @@ def test_sweep(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, wav
             nwg=o[1], ext_r0=o[2], ext_c0=o[3], own_r0=o[4], own_r1=o[5], own_c0=o[6], own_c1=o[7],
             cr=(o[8], o[9], o[10], o[11]), st=(o[12], o[13], o[14], o[15]), nb=[x for x in o[17:17 + o[16]]]))
     return [tiles[t] for t in sorted(tiles)]
+
+
+def test_batch(shapes, r64: int = 16, r32: int = 16, n_slots: int = 256):
+    """Batch planner without a GPU.  shapes: [(rows, cols, dtype, T), ...].
+    Returns (jobs, slot_lists) or None; jobs are dicts in global order, slot_lists[s] = [(job, member), ...]."""
+    n = len(shapes)
+    I64 = ctypes.c_int64 * n
+    rows = I64(*[s[0] for s in shapes])
+    cols = I64(*[s[1] for s in shapes])
+    dt = (ctypes.c_int32 * n)(*[s[2] for s in shapes])
+    T = I64(*[s[3] for s in shapes])
+    jobs = (ctypes.c_int32 * (n * 10))()
+    cap = n_slots + 1 + 2 * n * n_slots
+    lists = (ctypes.c_int32 * cap)()
+    rc = load().dtb_test_batch(n, rows, cols, dt, T, r64, r32, n_slots, jobs, lists, cap)
+    if rc < 0:
+        return None
+    keys = ("prob", "g", "sweep", "ntiles", "D", "nrounds", "flag_base", "table_off", "start", "dur")
+    jl = [dict(zip(keys, jobs[j * 10:(j + 1) * 10])) for j in range(rc)]
+    off = lists[:n_slots + 1]
+    pairs = lists[n_slots + 1:n_slots + 1 + 2 * off[-1]]
+    sl = [[(pairs[2 * i], pairs[2 * i + 1]) for i in range(off[s], off[s + 1])] for s in range(n_slots)]
+    return jl, sl

@@ -343,3 +343,51 @@ def test_sweep_full_size_16384_f32():
     err = oracle.rel_max_err(got, ref)
     print(f"[result] {w.name} plan={desc} T={T} FP32 rel max err vs FP64 oracle {err:.3e}")
     assert err <= 1e-5
+
+
+# ----------------------------------------------------------------------------- batched launch
+
+def _batch_refs(probs):
+    refs = []
+    for g, coeffs, T in probs:
+        u = g.cpu().numpy()
+        dt = u.dtype
+        refs.append(oracle.j2d5pt_f64(u.astype(np.float64), np.array(coeffs, dtype=dt).astype(np.float64), T))
+    return refs
+
+
+def test_batched_mixed_with_sweep_job_and_replay():
+    rng = np.random.default_rng(41)
+    shapes = [(130, 130, np.float64, 37), (257, 300, np.float32, 21), (64, 700, np.float32, 9), (1, 1, np.float64, 5),
+              (400, 410, np.float64, 50), (2100, 2100, np.float64, 30), (90, 3000, np.float64, 12)]
+    for call in range(2):  # the second call replays the graph with new grids and coefficients
+        probs = []
+        for rows, cols, dt, T in shapes:
+            coeffs = inputs.dirichlet_weights(rng)
+            u = inputs.uniform_grid(rows, cols, rng, halo=float(rng.uniform(0, 1)))
+            probs.append((_dev(u.astype(dt)), coeffs, T))
+        refs = _batch_refs(probs)
+        _say("batched call", call)
+        dtb.run_batched(probs)
+        dtb.batch_check()
+        for (g, coeffs, T), ref, shp in zip(probs, refs, shapes):
+            err = oracle.rel_max_err(g.cpu().numpy(), ref)
+            assert err <= (TOL_F64 if g.dtype == torch.float64 else 2e-5), (shp, err)
+
+
+def test_batched_equals_single_runs_fma():
+    """The batched kernel's fused chain per cell equals the single-grid kernels' (same tiling-invariant chain)."""
+    rng = np.random.default_rng(43)
+    shapes = [(200, 300, np.float64, 40), (333, 257, np.float32, 33), (150, 700, np.float64, 17)]
+    probs, singles = [], []
+    for rows, cols, dt, T in shapes:
+        coeffs = inputs.dirichlet_weights(rng)
+        u = inputs.uniform_grid(rows, cols, rng).astype(dt)
+        probs.append((_dev(u), coeffs, T))
+        s, _ = _run_plan(u, coeffs, T, dtype=dt, path=dtb.PATH_RESIDENT)
+        singles.append(s)
+    _say("batched vs single")
+    dtb.run_batched(probs)
+    dtb.batch_check()
+    for (g, _, _), s in zip(probs, singles):
+        assert np.array_equal(g.cpu().numpy(), s)

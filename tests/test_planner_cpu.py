@@ -82,13 +82,26 @@ def test_no_layout_when_ring_too_deep():
 
 # ----------------------------------------------------------------------------- tile-serial sweep
 
+def _rects_tile(rects, region):
+    """Rectangles [r0, r1) x [c0, c1) pairwise disjoint and covering `region` exactly."""
+    area = sum((r1 - r0) * (c1 - c0) for r0, r1, c0, c1 in rects)
+    R0, R1, C0, C1 = region
+    assert area == (R1 - R0) * (C1 - C0)
+    for r0, r1, c0, c1 in rects:
+        assert R0 <= r0 < r1 <= R1 and C0 <= c0 < c1 <= C1
+    for i in range(len(rects)):
+        a = rects[i]
+        for b in rects[i + 1:]:
+            assert not (a[0] < b[1] and b[0] < a[1] and a[2] < b[3] and b[2] < a[3]), (a, b)
+
+
 @pytest.mark.parametrize("case", [
     # rows, cols, R, C, waves, k, D, max_wg
     (600, 700, 8, 2, 8, 4, 16, 8),
     (1000, 333, 8, 2, 8, 3, 10, 6),
     (2048, 2048, 24, 2, 8, 8, 48, 64),
     (8192, 8192, 24, 2, 8, 8, 64, 256),
-    (16384, 16384, 20, 4, 8, 8, 64, 256),
+    (16384, 16384, 28, 4, 8, 8, 64, 256),
     (300, 5000, 16, 4, 8, 6, 20, 12),
 ], ids=lambda c: "x".join(map(str, c)))
 def test_sweep_plan_properties(case):
@@ -96,36 +109,73 @@ def test_sweep_plan_properties(case):
     ER, EC = waves * R, 64 * C
     tiles = dtb.test_sweep(rows, cols, R, C, waves, k, D, max_wg, 8)
     assert tiles is not None and len(tiles) >= 1
-    stored = np.zeros((rows + 2, cols + 2), dtype=np.int32)
+    valid = []
     for slots in tiles:
         nwg = slots[0]["nwg"]
         assert len(slots) == nwg <= max_wg
-        st = slots[0]["st"]
-        cr = slots[0]["cr"]
+        st, cr = slots[0]["st"], slots[0]["cr"]
         # the computed region is the valid part grown by D, clipped to the interior
         assert cr == (max(st[0] - D, 1), min(st[1] + D, rows + 1), max(st[2] - D, 1), min(st[3] + D, cols + 1))
-        stored[st[0]:st[1], st[2]:st[3]] += 1
-        active = [d for d in slots if d["own_r0"] < d["own_r1"]]
-        lay = [dict(d, narrow_rows=rows < ER, narrow_cols=cols < EC) for d in active]
-        # owned regions of the active slots tile the computed region exactly
-        owner = np.full((rows + 2, cols + 2), -1, dtype=np.int64)
-        slot_ids = [i for i, d in enumerate(slots) if d["own_r0"] < d["own_r1"]]
-        for i, d in zip(slot_ids, active):
-            blk = owner[d["own_r0"]:d["own_r1"], d["own_c0"]:d["own_c1"]]
-            assert np.all(blk == -1)
-            blk[...] = i
-            f_r0, f_r1 = max(d["own_r0"] - k, cr[0]), min(d["own_r1"] + k, cr[1])
-            f_c0, f_c1 = max(d["own_c0"] - k, cr[2]), min(d["own_c1"] + k, cr[3])
-            assert d["ext_r0"] <= f_r0 and f_r1 <= d["ext_r0"] + ER
-            assert d["ext_c0"] <= f_c0 and f_c1 <= d["ext_c0"] + EC
+        valid.append(st)
+        act = [(i, d) for i, d in enumerate(slots) if d["own_r0"] < d["own_r1"]]
+        owned = [(d["own_r0"], d["own_r1"], d["own_c0"], d["own_c1"]) for _, d in act]
+        _rects_tile(owned, cr)
+        for i, d in act:
+            f = (max(d["own_r0"] - k, cr[0]), min(d["own_r1"] + k, cr[1]),
+                 max(d["own_c0"] - k, cr[2]), min(d["own_c1"] + k, cr[3]))
+            assert d["ext_r0"] <= f[0] and f[1] <= d["ext_r0"] + ER
+            assert d["ext_c0"] <= f[2] and f[3] <= d["ext_c0"] + EC
             assert 1 <= d["ext_r0"] and (rows < ER or d["ext_r0"] + ER - 1 <= rows)
             assert 1 <= d["ext_c0"] and (cols < EC or d["ext_c0"] + EC - 1 <= cols)
-        assert np.all(owner[cr[0]:cr[1], cr[2]:cr[3]] >= 0)
-        assert np.sum(owner >= 0) == (cr[1] - cr[0]) * (cr[3] - cr[2])
-        for i, d in zip(slot_ids, active):
-            f = owner[max(d["own_r0"] - k, cr[0]):min(d["own_r1"] + k, cr[1]),
-                      max(d["own_c0"] - k, cr[2]):min(d["own_c1"] + k, cr[3])]
-            assert sorted(d["nb"]) == sorted(set(np.unique(f).tolist()) - {i})
+            want = sorted(j for j, o in act if j != i and o["own_r0"] < f[1] and o["own_r1"] > f[0]
+                          and o["own_c0"] < f[3] and o["own_c1"] > f[2])
+            assert sorted(d["nb"]) == want
     # valid parts partition the interior: every cell written exactly once per round
-    assert np.all(stored[1:rows + 1, 1:cols + 1] == 1)
-    assert stored.sum() == rows * cols
+    _rects_tile(valid, (1, rows + 1, 1, cols + 1))
+
+
+# ----------------------------------------------------------------------------- batched launch
+
+def _check_batch(shapes, n_slots=256):
+    res = dtb.test_batch(shapes, 16, 16, n_slots)
+    assert res is not None
+    jobs, lists = res
+    assert sorted(j["prob"] for j in jobs) == list(range(len(shapes)))
+    flags = set()
+    members = {j: [] for j in range(len(jobs))}
+    for s, lst in enumerate(lists):
+        order = [job for job, _ in lst]
+        assert order == sorted(order) and len(set(order)) == len(order), "slot work list not in global order"
+        for job, local in lst:
+            members[job].append(local)
+    for j, J in enumerate(jobs):
+        assert 1 <= J["g"] <= n_slots
+        assert sorted(members[j]) == list(range(J["g"]))
+        rng = set(range(J["flag_base"], J["flag_base"] + J["g"]))
+        assert not (rng & flags)
+        flags |= rng
+        if j:
+            assert jobs[j - 1]["start"] <= J["start"]
+    return jobs
+
+
+def test_batch_plan_config5():
+    from paper_2306_03336_amd import inputs
+    probs = inputs.batched_set(5)
+    jobs = _check_batch([(p.side, p.side, 0 if p.dtype == "f64" else 1, p.T) for p in probs])
+    assert any(j["sweep"] for j in jobs) or max(p.side for p in probs) < 1700
+
+
+def test_batch_plan_mixed_sizes():
+    shapes = [(1, 1, 0, 5), (3000, 3000, 0, 100), (50, 2000, 1, 7), (4000, 100, 1, 300), (130, 130, 0, 0),
+              (2100, 2100, 0, 30)]
+    jobs = _check_batch(shapes)
+    by_prob = {j["prob"]: j for j in jobs}
+    assert by_prob[0]["g"] == 1 and not by_prob[0]["sweep"]
+    assert by_prob[1]["sweep"] and by_prob[1]["ntiles"] >= 2
+    assert by_prob[5]["sweep"]
+
+
+def test_batch_plan_few_slots():
+    jobs = _check_batch([(300, 300, 0, 10), (300, 300, 1, 10), (1000, 1000, 0, 20)], n_slots=4)
+    assert max(j["g"] for j in jobs) <= 4
