@@ -80,7 +80,9 @@ typedef struct {
     int32_t max_wg;      /* cap on workgroups; 0 = every compute unit */
     int32_t exact;       /* 1: separately rounded products, plain left-to-right sum (bitwise CPU parity) */
     int32_t debug_flags; /* reserved, must be 0 */
-    int32_t reserved;
+    int32_t tune;        /* 1: time the best few candidate tilings on a scratch grid and keep the fastest
+                            (results cached per shape/precision/device, and in the text file named by the
+                            environment variable DTB_TUNE_CACHE if set); 0: static cost model only */
 } dtb_plan_opts;
 
 typedef struct dtb_plan_s* dtb_plan_t;

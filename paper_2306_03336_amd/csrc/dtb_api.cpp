@@ -1,5 +1,7 @@
 // dtb_api.cpp -- the libdtb C ABI: argument checks, plans, plan cache, launches.
 #include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -7,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -94,7 +97,7 @@ dtb_status check_opts(const dtb_plan_opts* o)
     if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_SWEEP) return DTB_ERR_INVALID_ARG;
     if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0) return DTB_ERR_INVALID_ARG;
     if (o->exact != 0 && o->exact != 1) return DTB_ERR_INVALID_ARG;
-    if (o->debug_flags != 0 || o->reserved != 0) return DTB_ERR_INVALID_ARG;
+    if (o->debug_flags != 0 || (o->tune != 0 && o->tune != 1)) return DTB_ERR_INVALID_ARG;
     return DTB_OK;
 }
 
@@ -210,7 +213,204 @@ bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o,
     return found;
 }
 
-dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, int dtype, int64_t /*T_hint*/,
+dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, int dtype, int64_t T_hint,
+                     const dtb_plan_opts* opts);
+dtb_status run_plan_impl(dtb_plan_t p, const dtb_grid* g, const double* coeffs, int64_t T, void* stream);
+
+// ---- autotuner: timed trials of the model's best candidates
+
+struct TuneChoice {
+    int path = 0, R = 0, k = 0, D = 0;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(int64_t rows, int64_t cols, int64_t pitch, int dtype, int exact, int64_t T_hint, int max_wg)
+{
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    // Step counts in power-of-two buckets: the best exchange/round depth changes slowly with T.
+    int tb = 0;
+    while ((int64_t(1) << tb) < T_hint && tb < 62) ++tb;
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%lld,%lld,%lld,%d,%d,%d,%d,%s,%d", (long long)rows, (long long)cols, (long long)pitch,
+             dtype, exact, tb, max_wg, prop.gcnArchName, prop.multiProcessorCount);
+    return buf;
+}
+
+void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("DTB_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+        // key<TAB>path R k D
+        char* tab = strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        TuneChoice c;
+        if (sscanf(tab + 1, "%d %d %d %d", &c.path, &c.R, &c.k, &c.D) == 4) g_tune[line] = c;
+    }
+    fclose(f);
+}
+
+void tune_cache_store(const std::string& key, const TuneChoice& c)
+{
+    g_tune[key] = c;
+    const char* path = getenv("DTB_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s\t%d %d %d %d\n", key.c_str(), c.path, c.R, c.k, c.D);
+    fclose(f);
+}
+
+// Candidates ranked by the static model, best first.
+std::vector<std::pair<double, TuneChoice>> tune_candidates(int64_t rows, int64_t cols, int dtype,
+                                                           const dtb_plan_opts& o, int n_cu)
+{
+    std::vector<std::pair<double, TuneChoice>> out;
+    const bool fma = o.exact == 0;
+    for (int R : kDtbRowsPerLane) {
+        if (o.rows_per_lane > 0 && o.rows_per_lane != R) continue;
+        int C = 0, waves = 0;
+        if (!dtb_kernel(dtype, R, fma, false, false, &C, &waves)) continue;
+        for (int k : {2, 4, 6, 8, 10, 12, 16}) {
+            if (o.ghost_k > 0 && o.ghost_k != k) continue;
+            if (o.path == DTB_PATH_AUTO || o.path == DTB_PATH_RESIDENT) {
+                Layout L;
+                if (build_layout(rows, cols, interior(rows, cols), interior(rows, cols), R, C, waves, k, kNumXcd, 0,
+                                 0, &L)) {
+                    const void* f = dtb_kernel(dtype, R, fma, L.cols.narrow, L.rows.narrow, &C, &waves);
+                    int occ = 0;
+                    if (f && !spills(f) &&
+                        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) == hipSuccess) {
+                        int cap = occ * n_cu;
+                        if (o.max_wg > 0) cap = std::min(cap, o.max_wg);
+                        if (L.nwg <= cap)
+                            out.push_back({layout_cost(L, occ, n_cu, 1.0) / (64.0 * 2400.0) * 7.0,
+                                           TuneChoice{DTB_PATH_RESIDENT, R, k, 0}});
+                    }
+                }
+            }
+            if (o.path == DTB_PATH_SWEEP || (o.path == DTB_PATH_AUTO && out.empty())) {
+                const bool cm = cols < kWaveSize * C, rc = rows < waves * R;
+                const void* f = dtb_sweep_kernel(dtype, R, fma, cm, rc, &C, &waves);
+                if (!f || spills(f)) continue;
+                const int cap = o.max_wg > 0 ? std::min(n_cu, o.max_wg) : n_cu;
+                for (int D : {16, 32, 48, 64, 96, 128, 192}) {
+                    if (o.depth_D > 0 && o.depth_D != D) continue;
+                    SweepPlan sp;
+                    if (!plan_sweep(rows, cols, R, C, waves, k, D, cap, kNumXcd, &sp)) continue;
+                    out.push_back({sweep_step_us(sp, dtype), TuneChoice{DTB_PATH_SWEEP, R, k, D}});
+                }
+            }
+        }
+    }
+    std::stable_sort(out.begin(), out.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    return out;
+}
+
+// Time a plan built with `c` on a zero-filled scratch grid: best of two runs of `steps` steps.
+double time_candidate(int64_t rows, int64_t cols, int64_t pitch, int dtype, const dtb_plan_opts& base,
+                      const TuneChoice& c, void* scratch, int64_t steps)
+{
+    dtb_plan_opts o = base;
+    o.tune = 0;
+    o.path = c.path;
+    o.rows_per_lane = c.R;
+    o.ghost_k = c.k;
+    o.depth_D = c.D;
+    dtb_plan_t p = nullptr;
+    if (plan_impl(&p, rows, cols, pitch, dtype, steps, &o) != DTB_OK) return 1e300;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best = 1e300;
+    const double coeffs[5] = {0.2, 0.2, 0.2, 0.2, 0.2};
+    const dtb_grid g{scratch, rows, cols, pitch};
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+        hipEventCreate(&e1) == hipSuccess) {
+        if (run_plan_impl(p, &g, coeffs, steps, st) == DTB_OK && hipStreamSynchronize(st) == hipSuccess) {
+            for (int rep = 0; rep < 2; ++rep) {
+                (void)hipEventRecord(e0, st);
+                if (run_plan_impl(p, &g, coeffs, steps, st) != DTB_OK) break;
+                (void)hipEventRecord(e1, st);
+                if (hipEventSynchronize(e1) != hipSuccess) break;
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best = std::min(best, (double)ms);
+            }
+        }
+        int e = 0;
+        if (p->d_err && hipMemcpy(&e, p->d_err, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess && e) best = 1e300;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    dtb_plan_destroy(p);
+    return best / steps;
+}
+
+dtb_status tune_plan(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, int dtype, int64_t T_hint,
+                     const dtb_plan_opts& o)
+{
+    DeviceInfo di;
+    if (!device_info(&di)) return DTB_ERR_HIP;
+    const std::string key = tune_key(rows, cols, pitch, dtype, o.exact, T_hint, o.max_wg);
+    TuneChoice choice;
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            choice = it->second;
+            have = true;
+        }
+    }
+    if (!have) {
+        auto cands = tune_candidates(rows, cols, dtype, o, di.n_cu);
+        if (cands.empty()) return DTB_ERR_NOT_CORESIDENT;
+        if (cands.size() > 6) cands.resize(6);
+        void* scratch = nullptr;
+        const size_t bytes = (size_t)(rows + 2) * (size_t)pitch * elem_size(dtype);
+        if (hipMalloc(&scratch, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMemset(scratch, 0, bytes) != hipSuccess) {
+            (void)hipFree(scratch);
+            return DTB_ERR_HIP;
+        }
+        double best = 1e300;
+        for (auto& c : cands) {
+            int64_t steps = c.second.path == DTB_PATH_SWEEP ? 2 * (int64_t)c.second.D : 8 * (int64_t)c.second.k;
+            if (T_hint > 0) steps = std::min<int64_t>(steps, std::max<int64_t>(T_hint, 1));
+            const double t = time_candidate(rows, cols, pitch, dtype, o, c.second, scratch, std::max<int64_t>(steps, 2));
+            if (t < best) {
+                best = t;
+                choice = c.second;
+                have = true;
+            }
+        }
+        (void)hipFree(scratch);
+        if (!have || best >= 1e299) return DTB_ERR_HIP;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_store(key, choice);
+    }
+    dtb_plan_opts fixed = o;
+    fixed.tune = 0;
+    fixed.path = choice.path;
+    fixed.rows_per_lane = choice.R;
+    fixed.ghost_k = choice.k;
+    fixed.depth_D = choice.D;
+    return plan_impl(out, rows, cols, pitch, dtype, T_hint, &fixed);
+}
+
+dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, int dtype, int64_t T_hint,
                      const dtb_plan_opts* opts)
 {
     if (!out) return DTB_ERR_INVALID_ARG;
@@ -221,6 +421,7 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
     if (st != DTB_OK) return st;
     dtb_plan_opts o{};
     if (opts) o = *opts;
+    if (o.tune && o.path != DTB_PATH_STEP) return tune_plan(out, rows, cols, pitch, dtype, T_hint, o);
 
     DeviceInfo di;
     if (!device_info(&di)) return DTB_ERR_HIP;

@@ -42,7 +42,7 @@ class Grid(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("ghost_k", ctypes.c_int32), ("depth_D", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("max_wg", ctypes.c_int32), ("exact", ctypes.c_int32),
-                ("debug_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("debug_flags", ctypes.c_int32), ("tune", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -153,10 +153,11 @@ class Plan:
     """An explicit plan (dtb_plan / dtb_run_plan / dtb_plan_destroy)."""
 
     def __init__(self, rows: int, cols: int, pitch: int, dtype: int, T_hint: int = 0, path: int = PATH_AUTO,
-                 ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0, exact: bool = False):
+                 ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0, exact: bool = False,
+                 tune: bool = False):
         lib = load()
         self._h = ctypes.c_void_p()
-        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, 0, 0)
+        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, 0, 1 if tune else 0)
         _check(lib.dtb_plan(ctypes.byref(self._h), rows, cols, pitch, dtype, T_hint, ctypes.byref(opts)), "dtb_plan")
         self.rows, self.cols, self.pitch, self.dtype = rows, cols, pitch, dtype
 
