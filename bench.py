@@ -15,7 +15,11 @@ Prints ONE JSON line.  Besides the headline value it carries:
                 on the launch stream;
   baseline_1step  the untiled one-launch-per-time-step kernel on the same
                 grid (T launches, HBM/Infinity-Cache bound), and DTB's speedup;
-  cpu_baseline  the CPU oracle on a bounded sample of the same workload.
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload;
+  other_configs the FP32 precision pair (3072^2 resident, 16384^2 swept for
+                400 of its 2000 steps), the 8192^2 FP64 tile-serial sweep, and
+                the 64-grid batch in one graph-replayed launch against the
+                same grids run one at a time.
 """
 from __future__ import annotations
 
@@ -50,6 +54,86 @@ def _cpu_baseline(w, budget_s: float):
             "sample": f"{w.rows}x{w.cols} FP64, {steps} of the {w.T} time steps ({dt:.1f} s, FP64, {nt} threads)"}
 
 
+def _time_run(plan, g, coeffs, T, torch, stream, reps=1):
+    """Best of `reps` runs of T steps, milliseconds (HIP events on the launch stream)."""
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.run(g, coeffs, T)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    plan.check()
+    return best
+
+
+def _one_config(dtb, inputs, torch, np, stream, name, T=None, warm=50):
+    w = inputs.workload(name)
+    dt = torch.float64 if w.dtype == "f64" else torch.float32
+    g = torch.from_numpy(w.grid()).to(device="cuda", dtype=dt)
+    T = w.T if T is None else T
+    plan = dtb.plan_for(g, w.T)
+    plan.run(g, w.coeffs, min(warm, T))
+    torch.cuda.synchronize()
+    ms = _time_run(plan, g, w.coeffs, T, torch, stream)
+    d = plan.describe()
+    plan.destroy()
+    del g
+    torch.cuda.empty_cache()
+    return {"workload": name, "dtype": w.dtype, "T_timed": T, "ms": round(ms, 3),
+            "GCells_per_s": round(w.rows * w.cols * T / (ms / 1e3) / 1e9, 2), "plan": d}
+
+
+def _batched(dtb, inputs, torch, np, stream):
+    probs = inputs.batched_set(5)
+    grids = []
+    for p in probs:
+        dt = torch.float64 if p.dtype == "f64" else torch.float32
+        grids.append((torch.from_numpy(p.grid()).to(device="cuda", dtype=dt), p.coeffs, p.T))
+    updates = sum(p.cell_updates for p in probs)
+    dtb.run_batched(grids)          # plans, allocates, builds the graph
+    dtb.batch_check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    dtb.run_batched(grids)          # graph replay
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dtb.batch_check()
+    ms = e0.elapsed_time(e1)
+    # The same grids one at a time through dtb_run (cached plans, built in a first pass).
+    for g, c, T in grids:
+        dtb.run(g, c, 1)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for g, c, T in grids:
+        dtb.run(g, c, T)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    return {"workload": "j2d5pt_batch64_seed5", "grids": len(probs), "cell_updates": updates,
+            "ms": round(ms, 3), "GCells_per_s": round(updates / (ms / 1e3) / 1e9, 2),
+            "one_at_a_time_ms": round(ms1, 3), "one_at_a_time_GCells_per_s": round(updates / (ms1 / 1e3) / 1e9, 2),
+            "batched_speedup": round(ms1 / ms, 3)}
+
+
+def _extras(dtb, inputs, torch, np, stream):
+    out = {}
+    jobs = [("fp32_resident_3072", lambda: _one_config(dtb, inputs, torch, np, stream, "j2d5pt_3072x3072_f32_T2000")),
+            ("fp64_sweep_8192", lambda: _one_config(dtb, inputs, torch, np, stream, "j2d5pt_8192x8192_f64_T1000")),
+            ("fp32_sweep_16384", lambda: _one_config(dtb, inputs, torch, np, stream, "j2d5pt_16384x16384_f32_T2000",
+                                                     T=400)),
+            ("batched_64", lambda: _batched(dtb, inputs, torch, np, stream))]
+    for key, fn in jobs:
+        print(f"[bench] {key}", file=sys.stderr, flush=True)
+        try:
+            out[key] = fn()
+        except Exception as e:  # a secondary configuration must not hide the headline line
+            out[key] = {"error": f"{type(e).__name__}: {e}"}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +143,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-step-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary configurations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -129,6 +214,10 @@ def main() -> int:
             "frac": round(achieved / peak, 4), "traffic": None,
             "kernel": "k_dtb", "avg_launch_ms": round(avg_ms, 4)}
 
+    extras = {}
+    if not args.no_extras:
+        extras = _extras(dtb, inputs, torch, np, stream)
+
     cpu = None if args.no_cpu else _cpu_baseline(w, args.cpu_budget)
 
     out = {
@@ -149,6 +238,7 @@ def main() -> int:
         "roofline": roof,
         "baseline_1step": base,
         "cpu_baseline": cpu,
+        "other_configs": extras,
     }
     print(json.dumps(out))
     plan.destroy()
