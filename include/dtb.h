@@ -79,11 +79,18 @@ typedef struct {
     int32_t rows_per_lane; /* register tile height per lane (instantiated sizes only); 0 = auto */
     int32_t max_wg;      /* cap on workgroups; 0 = every compute unit */
     int32_t exact;       /* 1: separately rounded products, plain left-to-right sum (bitwise CPU parity) */
-    int32_t debug_flags; /* reserved, must be 0 */
+    int32_t debug_flags; /* DTB_DEBUG_* bits; 0 in production */
     int32_t tune;        /* 1: time the best few candidate tilings on a scratch grid and keep the fastest
                             (results cached per shape/precision/device, and in the text file named by the
                             environment variable DTB_TUNE_CACHE if set); 0: static cost model only */
 } dtb_plan_opts;
+
+/* Debug bits for dtb_plan_opts.debug_flags. */
+#define DTB_DEBUG_TINY_SPIN 1 /* bounded in-kernel waits give up after a few polls: exercises the
+                                 DTB_ERR_TIMEOUT path (results are then wrong, the kernel still drains) */
+#define DTB_DEBUG_POISON 2    /* NaN-fill the exchange buffers before each run and every register cell
+                                 outside the k-deep fresh region at each exchange: a stale or unsynchronised
+                                 read, or a hole in the ghost ring, turns results into NaN */
 
 typedef struct dtb_plan_s* dtb_plan_t;
 

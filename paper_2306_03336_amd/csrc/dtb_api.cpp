@@ -65,6 +65,9 @@ struct dtb_plan_s {
     SweepPlan sweep;
     uint32_t* d_bar = nullptr;
     int nwg_launch = 0;
+    int debug = 0;
+
+    uint32_t spin_limit() const { return (debug & DTB_DEBUG_TINY_SPIN) ? 4u : kSpinLimit; }
 
     ~dtb_plan_s()
     {
@@ -97,7 +100,8 @@ dtb_status check_opts(const dtb_plan_opts* o)
     if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_SWEEP) return DTB_ERR_INVALID_ARG;
     if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0) return DTB_ERR_INVALID_ARG;
     if (o->exact != 0 && o->exact != 1) return DTB_ERR_INVALID_ARG;
-    if (o->debug_flags != 0 || (o->tune != 0 && o->tune != 1)) return DTB_ERR_INVALID_ARG;
+    if ((o->debug_flags & ~(DTB_DEBUG_TINY_SPIN | DTB_DEBUG_POISON)) != 0 || (o->tune != 0 && o->tune != 1))
+        return DTB_ERR_INVALID_ARG;
     return DTB_OK;
 }
 
@@ -432,6 +436,7 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
     p->pitch = pitch;
     p->dtype = dtype;
     p->fma = o.exact == 0;
+    p->debug = o.debug_flags;
     const size_t bytes = (size_t)(rows + 2) * (size_t)pitch * elem_size(dtype);
 
     int path = o.path;
@@ -514,8 +519,20 @@ dtb_status run_step(dtb_plan_t p, void* data, const double* coeffs, int64_t T, h
     return DTB_OK;
 }
 
+// Debug: fill the exchange buffers with NaN before a run, so a ghost cell
+// that was never published in this run shows up in the result.
+dtb_status poison_xbufs(dtb_plan_t p, hipStream_t st)
+{
+    if (!(p->debug & DTB_DEBUG_POISON)) return DTB_OK;
+    const size_t bytes = (size_t)(p->rows + 2) * (size_t)p->pitch * elem_size(p->dtype);
+    for (void* x : p->xbuf)
+        if (x && hipMemsetAsync(x, 0xFF, bytes, st) != hipSuccess) return DTB_ERR_HIP;
+    return DTB_OK;
+}
+
 dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t T, hipStream_t st)
 {
+    if (poison_xbufs(p, st) != DTB_OK) return DTB_ERR_HIP;
     ProbDesc P{};
     P.grid = data;
     P.xbuf[0] = p->xbuf[0];
@@ -531,11 +548,12 @@ dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t 
     P.fma = p->fma ? 1 : 0;
     P.narrow_cols = p->colmask ? 1 : 0;
     P.narrow_rows = p->rowcheck ? 1 : 0;
+    P.debug = p->debug;
     for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
     const WgDesc* wgs = p->d_wgs;
     uint32_t* flags = p->d_flags;
     int* err = p->d_err;
-    uint32_t spin = kSpinLimit;
+    uint32_t spin = p->spin_limit();
     void* args[] = {&P, (void*)&wgs, (void*)&flags, (void*)&err, &spin};
     const dim3 grid(p->layout.nwg), block(p->layout.waves * kWaveSize);
     if (hipLaunchCooperativeKernel(p->kfunc, grid, block, args, 0, st) != hipSuccess) return DTB_ERR_HIP;
@@ -544,6 +562,7 @@ dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t 
 
 dtb_status run_sweep(dtb_plan_t p, void* data, const double* coeffs, int64_t T, hipStream_t st)
 {
+    if (poison_xbufs(p, st) != DTB_OK) return DTB_ERR_HIP;
     const int rows = (int)p->rows, cols = (int)p->cols;
     const SweepPlan& sp = p->sweep;
     // The second buffer needs the grid's halo: the kernel reads it from whichever buffer is current.
@@ -564,6 +583,7 @@ dtb_status run_sweep(dtb_plan_t p, void* data, const double* coeffs, int64_t T, 
     P.fma = p->fma ? 1 : 0;
     P.narrow_cols = p->colmask ? 1 : 0;
     P.narrow_rows = p->rowcheck ? 1 : 0;
+    P.debug = p->debug;
     for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
     SweepArgs S{};
     S.bufs[0] = data;
@@ -578,7 +598,7 @@ dtb_status run_sweep(dtb_plan_t p, void* data, const double* coeffs, int64_t T, 
     const WgDesc* table = p->d_wgs;
     uint32_t* flags = p->d_flags;
     int* err = p->d_err;
-    uint32_t spin = kSpinLimit;
+    uint32_t spin = p->spin_limit();
     void* args[] = {&P, &S, (void*)&table, (void*)&flags, (void*)&err, &spin};
     const dim3 grid(p->nwg_launch), block(sp.waves * kWaveSize);
     if (hipLaunchCooperativeKernel(p->kfunc, grid, block, args, 0, st) != hipSuccess) return DTB_ERR_HIP;

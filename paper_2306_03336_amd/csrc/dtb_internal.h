@@ -28,7 +28,7 @@ struct ProbDesc {
     int32_t fma;         // 1: fused multiply-add chain; 0: separate products summed W,E,S,C,N
     int32_t narrow_cols; // 1 when some tile holds the east halo column inside it
     int32_t narrow_rows; // 1 when some tile holds the south halo row inside it
-    int32_t pad_;
+    int32_t debug;       // DTB_DEBUG_* bits (include/dtb.h)
     double coeffs[5];    // c, n, s, e, w
 };
 

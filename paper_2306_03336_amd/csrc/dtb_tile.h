@@ -239,6 +239,28 @@ struct Tile {
         }
     }
 
+    // Debug: set every interior cell of the register tile outside the fresh
+    // region (owned cells grown by k, clipped to the computed region) to NaN.
+    // Those cells are expendable by construction; a NaN reaching an owned
+    // cell within the next k steps would expose a hole in that argument.
+    __device__ __forceinline__ void poison(T (&x)[R][C], const WgDesc& d, int kk, int rows, int cols)
+    {
+        const int r_lo = max(d.own_r0 - kk, d.cr_r0), r_hi = min(d.own_r1 + kk, d.cr_r1);
+        const int c_lo = max(d.own_c0 - kk, d.cr_c0), c_hi = min(d.own_c1 + kk, d.cr_c1);
+        const T nan = __builtin_nan("");
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int g = g0 + r;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int col = col0 + c;
+                const bool interior = g >= 1 && g <= rows && col >= 1 && col <= cols;
+                const bool fresh = g >= r_lo && g < r_hi && col >= c_lo && col < c_hi;
+                if (interior && !fresh) x[r][c] = nan;
+            }
+        }
+    }
+
     // Owned cells inside the stored region -> dst.  SC1: device-scope stores
     // (the next round of the sweep reads them on other XCDs).
     template <bool SC1>
@@ -316,6 +338,8 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
     const int64_t pitch = P.pitch;
     int64_t done = 0;
     bool exchanged = false;
+    const bool poison = (P.debug & 2) != 0;
+    if (poison) t.poison(t.a, d, kk, rows, P.cols);
     while (done < steps) {
         const int64_t left = steps - done;
         const int nsteps = (int)(left < kk ? left : kk);
@@ -338,6 +362,7 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
             exchange_point(flags, me, d, base + epoch, err, spin_limit);
             exchanged = true;
             t.load_ghost(t.a, xb, pitch, d, kk);
+            if (poison) t.poison(t.a, d, kk, rows, P.cols);
         }
     }
     // Neighbours read their initial ghost ring from the source grid; when the

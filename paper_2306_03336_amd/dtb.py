@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdtb.so")
 
 F64, F32 = 0, 1
+DEBUG_TINY_SPIN, DEBUG_POISON = 1, 2
 PATH_AUTO, PATH_STEP, PATH_RESIDENT, PATH_SWEEP = 0, 1, 2, 3
 STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID_ARG", -2: "DTB_ERR_UNSUPPORTED", -3: "DTB_ERR_NOT_CORESIDENT",
           -4: "DTB_ERR_OUT_OF_MEMORY", -5: "DTB_ERR_HIP", -6: "DTB_ERR_TIMEOUT", -7: "DTB_ERR_NOT_PLANNED",
@@ -154,10 +155,10 @@ class Plan:
 
     def __init__(self, rows: int, cols: int, pitch: int, dtype: int, T_hint: int = 0, path: int = PATH_AUTO,
                  ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0, exact: bool = False,
-                 tune: bool = False):
+                 tune: bool = False, debug: int = 0):
         lib = load()
         self._h = ctypes.c_void_p()
-        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, 0, 1 if tune else 0)
+        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, debug, 1 if tune else 0)
         _check(lib.dtb_plan(ctypes.byref(self._h), rows, cols, pitch, dtype, T_hint, ctypes.byref(opts)), "dtb_plan")
         self.rows, self.cols, self.pitch, self.dtype = rows, cols, pitch, dtype
 

@@ -391,3 +391,55 @@ def test_batched_equals_single_runs_fma():
     dtb.batch_check()
     for (g, _, _), s in zip(probs, singles):
         assert np.array_equal(g.cpu().numpy(), s)
+
+
+# ----------------------------------------------------------------------------- debug aids, tuner, failure path
+
+@pytest.mark.parametrize("path,extra", [(dtb.PATH_RESIDENT, dict(ghost_k=5, rows_per_lane=8)),
+                                        (dtb.PATH_SWEEP, dict(ghost_k=4, depth_D=13, max_wg=9, rows_per_lane=8))],
+                         ids=["resident", "sweep"])
+def test_nan_poison_never_reaches_results(path, extra):
+    """Cells outside every tile's fresh ring and the exchange buffers are NaN-filled at each exchange;
+    the results must still equal the oracle bit for bit."""
+    rows, cols, T = 420, 650, 47
+    rng = np.random.default_rng(91)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols)
+    _say("poison", path, rows, cols, T)
+    got, _ = _run_plan(u, coeffs, T, path=path, exact=True, debug=dtb.DEBUG_POISON, **extra)
+    assert not np.isnan(got).any()
+    assert np.array_equal(got, oracle.j2d5pt_f64(u, coeffs, T))
+
+
+def test_watchdog_reports_timeout_and_drains():
+    """With the bounded waits cut to a few polls some workgroup gives up: the run still ends and
+    dtb_plan_check reports DTB_ERR_TIMEOUT (or, if nobody had to wait, the result is right)."""
+    rows, cols, T = 900, 900, 64
+    u = inputs.uniform_grid(rows, cols, 92)
+    g = _dev(u)
+    plan = dtb.plan_for(g, T, path=dtb.PATH_RESIDENT, ghost_k=2, rows_per_lane=8, debug=dtb.DEBUG_TINY_SPIN)
+    assert plan.describe()["workgroups"] > 8
+    _say("watchdog")
+    plan.run(g, inputs.EQUAL_WEIGHTS, T)
+    try:
+        plan.check()
+        timed_out = False
+    except dtb.DtbError as e:
+        assert e.status == -6
+        timed_out = True
+    if not timed_out:
+        assert oracle.rel_max_err(g.cpu().numpy(), oracle.j2d5pt_f64(u, inputs.EQUAL_WEIGHTS, T)) <= TOL_F64
+    plan.destroy()
+    # a normal plan afterwards works
+    got, _ = _run_plan(u, inputs.EQUAL_WEIGHTS, 10, path=dtb.PATH_RESIDENT)
+    assert oracle.rel_max_err(got, oracle.j2d5pt_f64(u, inputs.EQUAL_WEIGHTS, 10)) <= TOL_F64
+
+
+def test_tuned_plan_is_correct():
+    rows, cols, T = 1500, 1700, 120
+    coeffs = inputs.dirichlet_weights(93)
+    u = inputs.uniform_grid(rows, cols, 94)
+    _say("tuner", rows, cols)
+    got, desc = _run_plan(u, coeffs, T, tune=True)
+    print(f"[result] tuned plan {desc}")
+    assert oracle.rel_max_err(got, oracle.j2d5pt_f64(u, coeffs, T)) <= TOL_F64
