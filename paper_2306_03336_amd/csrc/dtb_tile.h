@@ -567,6 +567,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_dtb_sweep(ProbDesc P, SweepArgs 
         }
         done += steps;
     }
+    // A workgroup idle in the last tiles has not published its final epoch;
+    // every flag must end the run at the same value, since the next run
+    // starts counting from it.
+    if (threadIdx.x == 0) __hip_atomic_store(flags + me, base + epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 
@@ -662,6 +666,9 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
         }
         done += steps;
     }
+    // Members idle in the last tiles have not published their final epoch;
+    // every member's flag must end at the same value (the next run counts from it).
+    if (threadIdx.x == 0) __hip_atomic_store(flags + me, base + epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (J.nrounds & 1) {
         // The result is in the second buffer: copy the interior back.
         const int64_t n = (int64_t)rows * cols;

@@ -65,7 +65,9 @@ def test_exact_f64_bitwise(shape, R):
         try:
             got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_RESIDENT, ghost_k=k, rows_per_lane=R, exact=True)
         except dtb.DtbError as e:
-            assert e.status == -3 and 2 * k >= 64, (rows, cols, R, k, e)  # ring deeper than the tile
+            # Only the largest tile may be unavailable: its exact variant for grids narrower than the
+            # tile spills registers, and the planner never picks a spilling kernel.
+            assert e.status == -3 and R == 24 and (rows < 192 or cols < 128), (rows, cols, R, k, e)
             continue
         ref = oracle.j2d5pt_f64(u, coeffs, T)
         assert desc["path"] == dtb.PATH_RESIDENT and desc["exact"] == 1
@@ -277,6 +279,25 @@ def test_sweep_exact_bitwise(case):
         assert desc["path"] == dtb.PATH_SWEEP and desc["depth_D"] == D and desc["big_tiles"] >= 2, desc
         ref = oracle.j2d5pt_f64(u, coeffs, T)
         assert np.array_equal(got, ref), (case, float(np.max(np.abs(got - ref))))
+
+
+def test_sweep_plan_reused_across_runs():
+    """A sweep plan whose big tiles leave some workgroups idle, run several times in a row: every
+    run must start from consistent epoch flags (regression: idle workgroups once ended a run behind)."""
+    rows, cols = 900, 500
+    coeffs = inputs.dirichlet_weights(95)
+    u = inputs.uniform_grid(rows, cols, 96)
+    g = _dev(u)
+    plan = dtb.plan_for(g, 0, path=dtb.PATH_SWEEP, ghost_k=4, depth_D=12, max_wg=10, rows_per_lane=8, exact=True)
+    assert plan.describe()["big_tiles"] >= 3
+    total = 0
+    for T in (7, 30, 13, 25):
+        _say("sweep reuse", T)
+        plan.run(g, coeffs, T)
+        plan.check()
+        total += T
+    assert np.array_equal(g.cpu().numpy(), oracle.j2d5pt_f64(u, coeffs, total))
+    plan.destroy()
 
 
 def test_sweep_exact_f32_bitwise():
