@@ -477,26 +477,26 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
         const size_t nwg = (size_t)p->nwg_launch;
         if (hipMalloc(&p->ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMalloc(&p->d_wgs, n * sizeof(WgDesc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
-        if (hipMalloc(&p->d_flags, nwg * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_flags, nwg * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMalloc(&p->d_err, sizeof(int)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
-        if (hipMalloc(&p->d_bar, sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_bar, 17 * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         for (int i = 0; i < 2; ++i)
             if (hipMalloc(&p->xbuf[i], bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMemcpy(p->d_wgs, p->sweep.table.data(), n * sizeof(WgDesc), hipMemcpyHostToDevice) != hipSuccess)
             return DTB_ERR_HIP;
-        if (hipMemset(p->d_flags, 0, nwg * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+        if (hipMemset(p->d_flags, 0, nwg * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
         if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
-        if (hipMemset(p->d_bar, 0, sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+        if (hipMemset(p->d_bar, 0, 17 * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
     } else {
         const size_t nwg = p->layout.wgs.size();
         if (hipMalloc(&p->d_wgs, nwg * sizeof(WgDesc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
-        if (hipMalloc(&p->d_flags, nwg * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_flags, nwg * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMalloc(&p->d_err, sizeof(int)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         for (int i = 0; i < 2; ++i)
             if (hipMalloc(&p->xbuf[i], bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMemcpy(p->d_wgs, p->layout.wgs.data(), nwg * sizeof(WgDesc), hipMemcpyHostToDevice) != hipSuccess)
             return DTB_ERR_HIP;
-        if (hipMemset(p->d_flags, 0, nwg * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+        if (hipMemset(p->d_flags, 0, nwg * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
         if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
     }
     *out = p.release();
@@ -748,8 +748,10 @@ dtb_status make_batch(const dtb_problem* problems, int32_t count, int device, Ba
     if ((st = up((void**)&b->d_table, bp.table.data(), bp.table.size() * sizeof(WgDesc))) != DTB_OK) return st;
     if ((st = up((void**)&b->d_wl_off, bp.wl_off.data(), bp.wl_off.size() * sizeof(int))) != DTB_OK) return st;
     if ((st = up((void**)&b->d_wl, wl.data(), wl.size() * sizeof(WorkItem))) != DTB_OK) return st;
-    if (hipMalloc(&b->d_flags, std::max(bp.nflags, 1) * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
-    if (hipMemset(b->d_flags, 0, std::max(bp.nflags, 1) * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+    if (hipMalloc(&b->d_flags, (size_t)std::max(bp.nflags, 1) * kFlagStride * sizeof(uint32_t)) != hipSuccess)
+        return DTB_ERR_OUT_OF_MEMORY;
+    if (hipMemset(b->d_flags, 0, (size_t)std::max(bp.nflags, 1) * kFlagStride * sizeof(uint32_t)) != hipSuccess)
+        return DTB_ERR_HIP;
     if (hipMalloc(&b->d_err, sizeof(int)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
     if (hipMemset(b->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
     for (int i = 0; i < 2; ++i) {
@@ -893,7 +895,8 @@ dtb_status dtb_batch_check(void* stream)
         if (e != 0) {
             rc = DTB_ERR_TIMEOUT;
             if (hipMemset(b->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
-            if (hipMemset(b->d_flags, 0, (size_t)b->plan.nflags * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+            if (hipMemset(b->d_flags, 0, (size_t)b->plan.nflags * kFlagStride * sizeof(uint32_t)) != hipSuccess)
+                return DTB_ERR_HIP;
         }
     }
     return rc;
@@ -910,7 +913,7 @@ dtb_status dtb_plan_check(dtb_plan_t p, void* stream)
     // A timed-out run leaves the epoch counters out of step: reset them.
     if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
     const size_t nflags = p->path == DTB_PATH_SWEEP ? (size_t)p->nwg_launch : p->layout.wgs.size();
-    if (hipMemset(p->d_flags, 0, nflags * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+    if (hipMemset(p->d_flags, 0, nflags * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
     return DTB_ERR_TIMEOUT;
 }
 

@@ -11,6 +11,11 @@ namespace dtb {
 constexpr int kWaveSize = 64;
 constexpr int kMaxNeighbours = 24;
 
+// Epoch flags live kFlagStride uint32 apart (4 KiB): every flag in its own
+// cache line and, whatever the channel interleave, spread over the HBM
+// channels, so polling workgroups do not queue on one channel.
+constexpr int kFlagStride = 1024;
+
 // One problem of a launch: a grid advanced T steps in place.
 //
 // Storage (same for grid and the two exchange buffers): (rows + 2) lines of

@@ -25,7 +25,7 @@ const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowc
 struct SweepArgs {
     void* bufs[2];   // round r reads bufs[r & 1], writes bufs[(r + 1) & 1]; bufs[0] is the grid
     int32_t ntiles, nwg, D, nrounds;
-    uint32_t* bar;   // device-wide barrier counter (reset before every launch)
+    uint32_t* bar;   // device-wide barrier counters: 17 slots kFlagStride apart (reset before every launch)
 };
 
 hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st);

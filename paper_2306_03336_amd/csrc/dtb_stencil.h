@@ -11,6 +11,11 @@
 
 namespace dtb {
 
+// Fused multiply-add in the precision of the operands (v_fma_f32 for float,
+// v_fma_f64 for double; never a float promoted to double).
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 struct Coef {
     T c, n, s, e, w;
@@ -27,10 +32,10 @@ __device__ __forceinline__ T j2d5pt(T W, T E, T S, T C, T N, const Coef<T>& k)
 {
     if constexpr (FMA) {
         T acc = k.w * W;
-        acc = __builtin_fma(k.e, E, acc);
-        acc = __builtin_fma(k.s, S, acc);
-        acc = __builtin_fma(k.c, C, acc);
-        acc = __builtin_fma(k.n, N, acc);
+        acc = fma_t(k.e, E, acc);
+        acc = fma_t(k.s, S, acc);
+        acc = fma_t(k.c, C, acc);
+        acc = fma_t(k.n, N, acc);
         return acc;
     } else {
         T acc = k.w * W;

@@ -69,21 +69,21 @@ __device__ __forceinline__ T j2d5pt_edge(T W, T E, T S, T C, T N, T bw, T be, T 
 {
     if constexpr (FMA) {
         T acc;
-        if constexpr (BW && BE) acc = __builtin_fma(k.w, W, bwe);
-        else if constexpr (BW) acc = __builtin_fma(k.w, W, bw);
-        else if constexpr (BE) acc = __builtin_fma(k.w, W, be);
+        if constexpr (BW && BE) acc = fma_t(k.w, W, bwe);
+        else if constexpr (BW) acc = fma_t(k.w, W, bw);
+        else if constexpr (BE) acc = fma_t(k.w, W, be);
         else acc = k.w * W;
-        acc = __builtin_fma(k.e, E, acc);
-        acc = __builtin_fma(k.s, S, acc);
-        acc = __builtin_fma(k.c, C, acc);
-        acc = __builtin_fma(k.n, N, acc);
+        acc = fma_t(k.e, E, acc);
+        acc = fma_t(k.s, S, acc);
+        acc = fma_t(k.c, C, acc);
+        acc = fma_t(k.n, N, acc);
         return acc;
     } else {
         T acc;
-        if constexpr (BW) acc = __builtin_fma(k.w, W, bw);
+        if constexpr (BW) acc = fma_t(k.w, W, bw);
         else acc = k.w * W;
         T pe;
-        if constexpr (BE) pe = __builtin_fma(k.e, E, be);
+        if constexpr (BE) pe = fma_t(k.e, E, be);
         else pe = k.e * E;
         acc = acc + pe;
         acc = acc + k.s * S;
@@ -302,11 +302,11 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flags + me, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(flags + (size_t)me * kFlagStride, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((int)threadIdx.x < d.nnb) {
         const int nb = d.nb[threadIdx.x];
         uint32_t spins = 0;
-        while (!reached(__hip_atomic_load(flags + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
+        while (!reached(__hip_atomic_load(flags + (size_t)nb * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > spin_limit) {
                 __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_dtb(ProbDesc P, const WgDesc* __
     const int me = blockIdx.x;
     const WgDesc& d = wgs[me];
     char* lds = dtb_lds<T, C, R, WAVES>();
-    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t base = __hip_atomic_load(flags + (size_t)me * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t epoch = 0;
     T* grid = (T*)P.grid;
     if (halo_varies<T, C, R, WAVES, COLMASK>(P, d))
@@ -505,25 +505,47 @@ __global__ __launch_bounds__(WAVES * 64) void k_dtb(ProbDesc P, const WgDesc* __
                                                                            epoch, err, spin_limit, lds);
 }
 
-// Device-wide barrier for the sweep: a counter reset to 0 before the launch;
-// barrier number n (1-based) waits until it reaches n * gridDim.x.  Prior
-// device-scope stores are complete (vmcnt 0) before arriving.  Bounded wait
-// as in exchange_point.
-__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t target, int* err, uint32_t spin_limit)
+// Device-wide barrier for the sweep, two levels deep so that no address has
+// more than one XCD's workgroups polling it.  Counters (each in its own
+// kFlagStride slot, all reset to 0 before the launch): slot 0 counts XCDs,
+// slots 1..8 count arrivals per XCD, slots 9..16 are per-XCD release words.
+// Workgroup b runs on XCD b % 8.  Barrier number n (1-based): the last
+// arrival of an XCD bumps the XCD counter, waits for every XCD, then releases
+// its own XCD by writing n.  Prior device-scope stores are complete (vmcnt 0)
+// before arriving.  Bounded waits as in exchange_point.
+constexpr int kBarrierSlots = 17;
+
+__device__ __forceinline__ bool spin_until(uint32_t* p, uint32_t target, int* err, int code, uint32_t spin_limit)
+{
+    uint32_t spins = 0;
+    while (!reached(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > spin_limit) {
+            __hip_atomic_fetch_or(err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err, uint32_t spin_limit)
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t spins = 0;
-        while (!reached(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > spin_limit) {
-                __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        const uint32_t x = blockIdx.x % 8u;
+        const uint32_t per_xcd = (gridDim.x - x + 7u) / 8u;  // workgroups on this XCD
+        const uint32_t nxcd = gridDim.x < 8u ? gridDim.x : 8u;
+        uint32_t* xcnt = bar + (size_t)(1 + x) * kFlagStride;
+        uint32_t* xrel = bar + (size_t)(9 + x) * kFlagStride;
+        const uint32_t old = __hip_atomic_fetch_add(xcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == per_xcd * n) {
+            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            spin_until(bar, nxcd * n, err, 2, spin_limit);
+            __hip_atomic_store(xrel, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        spin_until(xrel, n, err, 2, spin_limit);
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -540,7 +562,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_dtb_sweep(ProbDesc P, SweepArgs 
 {
     const int me = blockIdx.x;
     char* lds = dtb_lds<T, C, R, WAVES>();
-    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t base = __hip_atomic_load(flags + (size_t)me * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t epoch = 0;
     uint32_t nbar = 0;
     int64_t done = 0;
@@ -563,14 +585,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_dtb_sweep(ProbDesc P, SweepArgs 
                                                                                   epoch, err, spin_limit, lds);
             }
             ++nbar;
-            grid_barrier(S.bar, nbar * gridDim.x, err, spin_limit);
+            grid_barrier(S.bar, nbar, err, spin_limit);
         }
         done += steps;
     }
     // A workgroup idle in the last tiles has not published its final epoch;
     // every flag must end the run at the same value, since the next run
     // starts counting from it.
-    if (threadIdx.x == 0) __hip_atomic_store(flags + me, base + epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(flags + (size_t)me * kFlagStride, base + epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 
@@ -586,10 +608,10 @@ __device__ __forceinline__ void group_point(uint32_t* flags, int flag_base, int 
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0)
-        __hip_atomic_store(flags + flag_base + local, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(flags + (size_t)(flag_base + local) * kFlagStride, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = threadIdx.x; i < g; i += blockDim.x) {
         uint32_t spins = 0;
-        while (!reached(__hip_atomic_load(flags + flag_base + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+        while (!reached(__hip_atomic_load(flags + (size_t)(flag_base + i) * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                         target)) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > spin_limit) {
@@ -612,7 +634,7 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
                                         int local, uint32_t* flags, int* err, uint32_t spin_limit, char* lds)
 {
     const int me = J.flag_base + local;
-    const uint32_t base = __hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t base = __hip_atomic_load(flags + (size_t)me * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t epoch = 0;
     T* grid = (T*)P.grid;
     if (!J.sweep) {
@@ -668,7 +690,7 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
     }
     // Members idle in the last tiles have not published their final epoch;
     // every member's flag must end at the same value (the next run counts from it).
-    if (threadIdx.x == 0) __hip_atomic_store(flags + me, base + epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(flags + (size_t)me * kFlagStride, base + epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (J.nrounds & 1) {
         // The result is in the second buffer: copy the interior back.
         const int64_t n = (int64_t)rows * cols;
