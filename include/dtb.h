@@ -91,6 +91,10 @@ typedef struct {
 #define DTB_DEBUG_POISON 2    /* NaN-fill the exchange buffers before each run and every register cell
                                  outside the k-deep fresh region at each exchange: a stale or unsynchronised
                                  read, or a hole in the ghost ring, turns results into NaN */
+#define DTB_DEBUG_TIMING 4    /* per-workgroup phase clocks (steps, publishing border strips, waiting for
+                                 neighbours, loading the ghost ring): read them with dtb_plan_timing */
+#define DTB_DEBUG_DIRECT_XCHG 8 /* move border strips lane by lane between registers and the exchange
+                                   buffer instead of through the LDS staging area (same results) */
 
 typedef struct dtb_plan_s* dtb_plan_t;
 
@@ -153,6 +157,19 @@ dtb_status dtb_batch_check(void* stream);
  * (DTB_ERR_TIMEOUT) recorded since the previous check; clears it.
  */
 dtb_status dtb_plan_check(dtb_plan_t plan, void* stream);
+
+/*
+ * Phase clocks of a plan made with DTB_DEBUG_TIMING, accumulated over its runs
+ * since the previous call (which this call resets): waits for `stream`, then
+ * fills up to `n` uint64 values, 8 per workgroup in launch order: ticks (of
+ * the GPU's 100 MHz real-time clock) spent in steps, publishing border strips,
+ * waiting for neighbours, loading the ghost ring; number of exchanges; total
+ * ticks; then, when border strips go through the LDS staging area, the ticks
+ * spent moving the published strips from registers to LDS and the loaded
+ * ring from the buffer to LDS (not counted in the publishing and loading
+ * figures).  DTB_ERR_NOT_PLANNED if the plan has no clocks.
+ */
+dtb_status dtb_plan_timing(dtb_plan_t plan, uint64_t* out, int32_t n, void* stream);
 
 /*
  * Describe a plan: fills up to `n` int64 values in this order: path,

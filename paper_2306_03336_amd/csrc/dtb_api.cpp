@@ -66,6 +66,7 @@ struct dtb_plan_s {
     uint32_t* d_bar = nullptr;
     int nwg_launch = 0;
     int debug = 0;
+    uint64_t* d_timing = nullptr;  // DTB_DEBUG_TIMING
 
     uint32_t spin_limit() const { return (debug & DTB_DEBUG_TINY_SPIN) ? 4u : kSpinLimit; }
 
@@ -73,6 +74,7 @@ struct dtb_plan_s {
     {
         if (ws) (void)hipFree(ws);
         if (d_bar) (void)hipFree(d_bar);
+        if (d_timing) (void)hipFree(d_timing);
         if (d_wgs) (void)hipFree(d_wgs);
         if (d_flags) (void)hipFree(d_flags);
         if (d_err) (void)hipFree(d_err);
@@ -100,7 +102,8 @@ dtb_status check_opts(const dtb_plan_opts* o)
     if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_SWEEP) return DTB_ERR_INVALID_ARG;
     if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0) return DTB_ERR_INVALID_ARG;
     if (o->exact != 0 && o->exact != 1) return DTB_ERR_INVALID_ARG;
-    if ((o->debug_flags & ~(DTB_DEBUG_TINY_SPIN | DTB_DEBUG_POISON)) != 0 || (o->tune != 0 && o->tune != 1))
+    if ((o->debug_flags & ~(DTB_DEBUG_TINY_SPIN | DTB_DEBUG_POISON | DTB_DEBUG_TIMING | DTB_DEBUG_DIRECT_XCHG)) != 0 ||
+        (o->tune != 0 && o->tune != 1))
         return DTB_ERR_INVALID_ARG;
     return DTB_OK;
 }
@@ -499,6 +502,11 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
         if (hipMemset(p->d_flags, 0, nwg * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
         if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
     }
+    if ((p->debug & DTB_DEBUG_TIMING) && path != DTB_PATH_STEP) {
+        const size_t n = (size_t)std::max<int>(p->nwg_launch, p->layout.nwg) * kTimingSlots;
+        if (hipMalloc(&p->d_timing, n * sizeof(uint64_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMemset(p->d_timing, 0, n * sizeof(uint64_t)) != hipSuccess) return DTB_ERR_HIP;
+    }
     *out = p.release();
     return DTB_OK;
 }
@@ -549,6 +557,8 @@ dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t 
     P.narrow_cols = p->colmask ? 1 : 0;
     P.narrow_rows = p->rowcheck ? 1 : 0;
     P.debug = p->debug;
+    P.timing = p->d_timing;
+    P.direct_xchg = (p->debug & DTB_DEBUG_DIRECT_XCHG) ? 1 : 0;
     for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
     const WgDesc* wgs = p->d_wgs;
     uint32_t* flags = p->d_flags;
@@ -584,6 +594,8 @@ dtb_status run_sweep(dtb_plan_t p, void* data, const double* coeffs, int64_t T, 
     P.narrow_cols = p->colmask ? 1 : 0;
     P.narrow_rows = p->rowcheck ? 1 : 0;
     P.debug = p->debug;
+    P.timing = p->d_timing;
+    P.direct_xchg = (p->debug & DTB_DEBUG_DIRECT_XCHG) ? 1 : 0;
     for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
     SweepArgs S{};
     S.bufs[0] = data;
@@ -915,6 +927,19 @@ dtb_status dtb_plan_check(dtb_plan_t p, void* stream)
     const size_t nflags = p->path == DTB_PATH_SWEEP ? (size_t)p->nwg_launch : p->layout.wgs.size();
     if (hipMemset(p->d_flags, 0, nflags * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
     return DTB_ERR_TIMEOUT;
+}
+
+dtb_status dtb_plan_timing(dtb_plan_t p, uint64_t* out, int32_t n, void* stream)
+{
+    if (!p || n < 0 || (n > 0 && !out)) return DTB_ERR_INVALID_ARG;
+    if (!p->d_timing) return DTB_ERR_NOT_PLANNED;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return DTB_ERR_HIP;
+    const int nwg = std::max<int>(p->nwg_launch, p->layout.nwg);
+    const size_t m = std::min<size_t>((size_t)n, (size_t)nwg * kTimingSlots);
+    if (m && hipMemcpy(out, p->d_timing, m * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return DTB_ERR_HIP;
+    if (hipMemset(p->d_timing, 0, (size_t)nwg * kTimingSlots * sizeof(uint64_t)) != hipSuccess) return DTB_ERR_HIP;
+    return DTB_OK;
 }
 
 dtb_status dtb_plan_describe(dtb_plan_t p, int64_t* v, int32_t n)

@@ -35,7 +35,20 @@ struct ProbDesc {
     int32_t narrow_rows; // 1 when some tile holds the south halo row inside it
     int32_t debug;       // DTB_DEBUG_* bits (include/dtb.h)
     double coeffs[5];    // c, n, s, e, w
+    uint64_t* timing;    // DTB_DEBUG_TIMING: kTimingSlots counters per workgroup, else null
+    int32_t direct_xchg; // 1: exchange border strips lane by lane, never through the LDS staging area
+    int32_t pad_;
 };
+
+// Per-workgroup phase timing (s_memrealtime ticks, 100 MHz): time in steps,
+// in publishing border strips (stores and their completion), waiting for
+// neighbours' flags, loading the ghost ring, and the number of exchanges.
+constexpr int kTimingSlots = 8;
+// With the LDS staging area, publishing and loading are each split in two:
+// kTimeStageOut (registers to LDS) + kTimePublish (LDS to the buffer), and
+// kTimeStageIn (buffer to LDS) + kTimeGhost (LDS to registers).
+enum TimingSlot { kTimeSteps = 0, kTimePublish = 1, kTimeWait = 2, kTimeGhost = 3, kTimeExchanges = 4,
+                  kTimeTotal = 5, kTimeStageOut = 6, kTimeStageIn = 7 };
 
 // One workgroup: which problem, where its register tile sits, what it owns.
 //

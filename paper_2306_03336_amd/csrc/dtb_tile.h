@@ -39,6 +39,33 @@ namespace dtb {
 
 // ============================================================================ deep temporal blocking
 
+// How border strips travel between workgroups.  0: device-scope (sc1) stores
+// and loads, ordered by s_waitcnt; 1: plain (L2-cached) stores and loads with
+// one agent-scope release (L2 write-back) / acquire (L2 invalidate) per
+// workgroup per exchange.
+#ifndef DTB_XCHG_MODE
+#define DTB_XCHG_MODE 0
+#endif
+
+template <typename T>
+__device__ __forceinline__ void xchg_store(T* p, T v)
+{
+#if DTB_XCHG_MODE == 0
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+    *p = v;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ T xchg_load(T* p)
+{
+#if DTB_XCHG_MODE == 0
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+    return *p;
+#endif
+}
+
 // DPP wave shifts (GFX9 wave_shr:1 / wave_shl:1) with bound_ctrl: a lane
 // whose source lane does not exist (lane 0 for shr, lane 63 for shl) reads 0.
 template <typename T>
@@ -104,8 +131,72 @@ struct Geo {
     // zeros (what every other lane reads on the row-by-row halo path).
     static constexpr int kEdgeElems = 2 * (WAVES + 2) * 2 * EC;
     static constexpr int kHaloElems = ER * 3;
-    static constexpr size_t kLdsBytes = (size_t)(kEdgeElems + kHaloElems) * sizeof(T);
+    // Exchange staging area for rings up to kStageK deep (deeper rings take
+    // the direct per-lane path): a block of up to 2 * kStageK full-width rows
+    // (EC cells each) and a block of ER side rows (kSide left cells, then
+    // kSide right cells each).
+    // Tiles whose two register sets take more than 192 VGPRs per lane have
+    // no room for the staging code and always exchange lane by lane.
+    static constexpr bool kStaged = 2 * R * C * (int)sizeof(T) / 4 <= 192;
+    static constexpr int kStageK = R >= 16 ? 12 : 8;
+    static constexpr int kSide = kStageK <= 8 ? 8 : 16;
+    static constexpr int kStageRows = 2 * kStageK * EC;
+    static constexpr int kStageElems = kStaged ? kStageRows + ER * 2 * kSide : 0;
+    // ... followed by one spare slot per lane (see stage_cells).
+    static constexpr int kStageSpare = kStaged ? kWaveSize : 0;
+    static constexpr size_t kLdsBytes = (size_t)(kEdgeElems + kHaloElems + kStageElems + kStageSpare) * sizeof(T);
 };
+
+// What one exchange moves, laid out for the LDS staging area: the full-width
+// rows [n0, n1) and [s0, s1) over the columns [c0, c1) (each stored as a whole
+// tile row of EC cells), then the side rows [m0, m1) over the columns
+// [w0, w1) (left part) and [e0, e1) (right part).
+// The rim a tile publishes is its owned cells within k of an owned edge; the
+// ring it loads is the cells within k of its owned region, inside its
+// computed region, that it does not own.
+struct StageMap {
+    int n0, n1, s0, s1, c0, c1;
+    int m0, m1, w0, w1, e0, e1;
+    int tc0;  // c0 - the tile's first column: full rows are stored by tile column
+};
+
+__device__ __forceinline__ StageMap rim_map(const WgDesc& d, int kk)
+{
+    StageMap m;
+    m.n0 = d.own_r0;
+    m.n1 = min(d.own_r0 + kk, d.own_r1);
+    m.s0 = max(d.own_r1 - kk, m.n1);
+    m.s1 = d.own_r1;
+    m.c0 = d.own_c0;
+    m.c1 = d.own_c1;
+    m.m0 = m.n1;
+    m.m1 = m.s0;
+    m.w0 = d.own_c0;
+    m.w1 = min(d.own_c0 + kk, d.own_c1);
+    m.e0 = max(d.own_c1 - kk, m.w1);
+    m.e1 = d.own_c1;
+    m.tc0 = m.c0 - d.ext_c0;
+    return m;
+}
+
+__device__ __forceinline__ StageMap ring_map(const WgDesc& d, int kk)
+{
+    StageMap m;
+    m.n0 = max(d.own_r0 - kk, d.cr_r0);
+    m.n1 = d.own_r0;
+    m.s0 = d.own_r1;
+    m.s1 = min(d.own_r1 + kk, d.cr_r1);
+    m.c0 = max(d.own_c0 - kk, d.cr_c0);
+    m.c1 = min(d.own_c1 + kk, d.cr_c1);
+    m.m0 = d.own_r0;
+    m.m1 = d.own_r1;
+    m.w0 = m.c0;
+    m.w1 = d.own_c0;
+    m.e0 = d.own_c1;
+    m.e1 = m.c1;
+    m.tc0 = m.c0 - d.ext_c0;
+    return m;
+}
 
 template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
 struct Tile {
@@ -117,6 +208,7 @@ struct Tile {
     T b[R][C];
 
     T* edge;         // LDS edge rows
+    T* stage;        // LDS exchange staging area (Geo::kStageElems)
     const T* hbw;    // LDS, per lane: the west products (lane 0) or zeros
     const T* hbe;    // LDS, per lane: the east products (lane 63) or zeros
     const T* hbwe;   // LDS, per lane: lane 0 west, lane 63 east, zeros elsewhere
@@ -199,6 +291,13 @@ struct Tile {
     // without an L2 write-back.
     __device__ __forceinline__ void publish(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk)
     {
+        // Every store below sits in its own exec-masked block, so the
+        // compiler's wait-count tracking cannot see that the tile registers
+        // are no longer the target of an outstanding load (the paths into the
+        // step loop include the ghost loads) and would otherwise put a
+        // vmcnt(0) wait before each store, serialising them.  One explicit
+        // wait here (nothing is outstanding by now) clears that state.
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt/lgkmcnt untouched
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int g = g0 + r;
@@ -209,9 +308,7 @@ struct Tile {
                 const int col = col0 + c;
                 const bool own = col >= d.own_c0 && col < d.own_c1;
                 const bool near = row_near || col < d.own_c0 + kk || col >= d.own_c1 - kk;
-                if (own && near)
-                    __hip_atomic_store(xb + (int64_t)g * pitch + col, x[r][c], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                if (own && near) xchg_store(xb + (int64_t)g * pitch + col, x[r][c]);
             }
         }
     }
@@ -232,10 +329,150 @@ struct Tile {
                 const int col = col0 + c;
                 const bool in_ring = col >= c_lo && col < c_hi;
                 const bool own = row_own && col >= d.own_c0 && col < d.own_c1;
-                if (in_ring && !own)
-                    x[r][c] = __hip_atomic_load(xb + (int64_t)g * pitch + col, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
+                if (in_ring && !own) x[r][c] = xchg_load(xb + (int64_t)g * pitch + col);
             }
+        }
+    }
+
+    // Move this lane's cells of a stage map between registers and the
+    // staging area (LOAD: stage -> registers).  A full row is stored as the
+    // whole tile row (slot = tile column), so every lane has a slot there;
+    // side rows hold only the side columns, and a lane with nothing to move
+    // in a side row uses a spare slot of its own past the staging area.
+    // Branch-free: lane r works out the kind and first slot of row r, read
+    // back as a scalar, so each cell costs one select and one LDS access,
+    // and the accesses issue back to back.
+    template <bool LOAD>
+    __device__ __forceinline__ void stage_cells(T (&x)[R][C], const StageMap& m)
+    {
+        constexpr int kSide = G::kSide;
+        // An opaque copy of col0: keeps the compiler from hoisting the column
+        // offsets out of the epoch loop, where they would stay live (and
+        // spill) through the steps.
+        int lcol0 = col0;
+        asm volatile("" : "+v"(lcol0));
+        if constexpr (!LOAD) __builtin_amdgcn_s_waitcnt(0x0F70);  // as in publish: no wait per LDS store
+        const int spare = G::kStageElems + lane;
+        const int lslot = lane * C;
+        // Per column slot: in the map's full-row columns (nm = -1), a side
+        // column (wm = -1, side slot weoff).  Masks rather than bools: the
+        // selects below are then plain bit operations on values.
+        int nm[C], wm[C], weoff[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int col = lcol0 + c;
+            nm[c] = (col >= m.c0 && col < m.c1) ? -1 : 0;
+            const bool w = col >= m.w0 && col < m.w1, e = col >= m.e0 && col < m.e1;
+            wm[c] = (w || e) ? -1 : 0;
+            weoff[c] = w ? col - m.w0 : kSide + col - m.e0;
+        }
+        // Row r of this wave: bit 31 set for a full row (low bits: its first
+        // slot), a side row's first slot, or -1 when the row moves nothing.
+        int rowinfo;
+        {
+            const int g = g0 + (lane < R ? lane : 0);
+            const int nn = m.n1 - m.n0;
+            const bool in_n = g >= m.n0 && g < m.n1, in_s = g >= m.s0 && g < m.s1, in_m = g >= m.m0 && g < m.m1;
+            rowinfo = in_n ? (int)(0x80000000u | (uint32_t)((g - m.n0) * EC))
+                    : in_s ? (int)(0x80000000u | (uint32_t)((nn + g - m.s0) * EC))
+                    : in_m ? G::kStageRows + (g - m.m0) * 2 * kSide
+                           : -1;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int info = __builtin_amdgcn_readlane(rowinfo, r);
+            const int fm = (info < 0 && info != -1) ? -1 : 0;  // full row
+            const int sm = info >= 0 ? -1 : 0;                 // side row
+            const int base = info & 0x7fffffff;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                // A lane moves the cell when the row is full and the column is
+                // in the map's columns, or the row is a side row and the
+                // column a side column.
+                const int sw = sm & wm[c];
+                const bool live = ((fm & nm[c]) | sw) != 0;
+                const int slot = (fm & (base + lslot + c)) | (~fm & ((sw & (base + weoff[c])) | (~sw & spare)));
+                if constexpr (LOAD) {
+                    const T v = stage[slot];
+                    x[r][c] = live ? v : x[r][c];
+                } else {
+                    stage[slot] = x[r][c];
+                }
+            }
+            // Groups of four rows: enough accesses in flight to cover the LDS
+            // latency without holding a register pair per cell.
+            if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    // Copy a stage map between the staging area and the exchange buffer
+    // (STORE: stage -> buffer) with the whole workgroup: full rows with EC
+    // consecutive lanes per row (a wave covers part of one row, so the row is
+    // scalar), side rows with 2 * kSide lanes per row.  Buffer addresses step
+    // by scalar strides and staging slots by immediate offsets; all loads (or
+    // LDS reads) are issued before any of their results is used, so one
+    // memory latency covers the lot.
+    template <bool STORE>
+    __device__ __forceinline__ void stage_copy(T* xb, int64_t pitch, const StageMap& m)
+    {
+        constexpr int kThreads = WAVES * kWaveSize;
+        constexpr int kSide = G::kSide, SW = 2 * kSide;
+        constexpr int kRowsPass = kThreads / EC, kSidePass = kThreads / SW;
+        constexpr int kNP = (2 * G::kStageK + kRowsPass - 1) / kRowsPass;
+        constexpr int kSP = (ER + kSidePass - 1) / kSidePass;
+        static_assert(kThreads % EC == 0 && kThreads % SW == 0 && EC % kWaveSize == 0, "staging copy shape");
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));  // as in stage_cells: no hoisting out of the epoch loop
+        const int nn = m.n1 - m.n0, nrows = nn + (m.s1 - m.s0);
+        const int cc = tid % EC;
+        const int rr = uniform(tid / EC);  // the same for the whole wave
+        const bool cact = cc < m.c1 - m.c0;
+        T* const fbase = xb + m.c0 + cc;
+        T* const fslot = stage + rr * EC + m.tc0 + cc;
+        const int sc = tid % SW, sr = tid / SW;
+        const bool left = sc < kSide;
+        const int scol = left ? m.w0 + sc : m.e0 + (sc - kSide);
+        const bool sact = left ? sc < m.w1 - m.w0 : (sc - kSide) < m.e1 - m.e0;
+        const int nm = m.m1 - m.m0;
+        T* const sbase = xb + (int64_t)(m.m0 + sr) * pitch + scol;
+        T* const sslot = stage + G::kStageRows + sr * SW + sc;
+        const int64_t sstride = (int64_t)kSidePass * pitch;
+        T v[kNP + kSP];
+        if constexpr (STORE) {
+#pragma unroll
+            for (int j = 0; j < kNP; ++j) v[j] = fslot[j * kRowsPass * EC];
+#pragma unroll
+            for (int j = 0; j < kSP; ++j) v[kNP + j] = sslot[j * kSidePass * SW];
+#pragma unroll
+            for (int j = 0; j < kNP; ++j) {
+                const int ri = rr + j * kRowsPass;
+                if (ri < nrows && cact) {
+                    const int g = ri < nn ? m.n0 + ri : m.s0 + (ri - nn);
+                    xchg_store(fbase + (int64_t)g * pitch, v[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kSP; ++j)
+                if (sr + j * kSidePass < nm && sact) xchg_store(sbase + j * sstride, v[kNP + j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kNP; ++j) {
+                const int ri = rr + j * kRowsPass;
+                const int g = ri < nn ? m.n0 + ri : m.s0 + (ri - nn);
+                v[j] = (ri < nrows && cact) ? xchg_load(fbase + (int64_t)g * pitch) : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < kSP; ++j)
+                v[kNP + j] = (sr + j * kSidePass < nm && sact) ? xchg_load(sbase + j * sstride) : T(0);
+            // Only live positions write: a full-row slot of a lane past the
+            // row's columns can lie in the next row, and past the last row in
+            // the side block.
+#pragma unroll
+            for (int j = 0; j < kNP; ++j)
+                if (rr + j * kRowsPass < nrows && cact) fslot[j * kRowsPass * EC] = v[j];
+#pragma unroll
+            for (int j = 0; j < kSP; ++j)
+                if (sr + j * kSidePass < nm && sact) sslot[j * kSidePass * SW] = v[kNP + j];
         }
     }
 
@@ -268,6 +505,7 @@ struct Tile {
     {
         const int r0 = max(d.own_r0, d.st_r0), r1 = min(d.own_r1, d.st_r1);
         const int c0 = max(d.own_c0, d.st_c0), c1 = min(d.own_c1, d.st_c1);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // as in publish: keeps the stores from being serialised
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int g = g0 + r;
@@ -302,6 +540,9 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+#if DTB_XCHG_MODE == 1
+    if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#endif
     if (threadIdx.x == 0) __hip_atomic_store(flags + (size_t)me * kFlagStride, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((int)threadIdx.x < d.nnb) {
         const int nb = d.nb[threadIdx.x];
@@ -316,6 +557,9 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
             if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         }
     }
+#if DTB_XCHG_MODE == 1
+    if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#endif
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 }
@@ -326,7 +570,7 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
 // tail step is copied back.  A run of k steps is followed by an exchange
 // point (a workgroup barrier), so an odd k never lets two consecutive steps
 // share a parity.
-template <bool HALO_ROWS, typename Tl>
+template <bool HALO_ROWS, bool STAGED, typename Tl>
 __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDesc& d, int64_t steps, int me,
                                            uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
                                            uint32_t spin_limit)
@@ -340,6 +584,14 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
     bool exchanged = false;
     const bool poison = (P.debug & 2) != 0;
     if (poison) t.poison(t.a, d, kk, rows, P.cols);
+    // Exchanges go through the LDS staging area unless the ring is deeper than it holds.
+    using Tile_ = typename std::remove_reference<Tl>::type;
+    constexpr bool kStagedHere = STAGED && Tile_::G::kStaged;
+    const bool staged = kStagedHere && !P.direct_xchg && kk <= Tile_::G::kStageK;
+    // DTB_DEBUG_TIMING: phase clocks of thread 0 (uniform branch, off by default).
+    const bool timing = P.timing != nullptr;
+    uint64_t tm[kTimingSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t t0 = timing ? __builtin_amdgcn_s_memrealtime() : 0, t_start = t0;
     while (done < steps) {
         const int64_t left = steps - done;
         const int nsteps = (int)(left < kk ? left : kk);
@@ -357,12 +609,94 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
         done += nsteps;
         if (done < steps) {
             T* xb = (T*)P.xbuf[epoch & 1];
-            t.publish(t.a, xb, pitch, d, kk);
+            if (timing) {
+                __syncthreads();
+                const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+                tm[kTimeSteps] += t1 - t0;
+                t0 = t1;
+            }
+            // An opaque copy of k keeps the maps from being hoisted out of the loop.
+            int kx = kk;
+            asm volatile("" : "+s"(kx));
+            if constexpr (kStagedHere) {
+                if (staged) {
+                    const StageMap m = rim_map(d, kx);
+                    t.template stage_cells<false>(t.a, m);
+                    __syncthreads();
+                    if (timing) {
+                        const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+                        tm[kTimeStageOut] += t1 - t0;
+                        t0 = t1;
+                    }
+                    t.template stage_copy<true>(xb, pitch, m);
+                } else {
+                    t.publish(t.a, xb, pitch, d, kk);
+                }
+            } else {
+                t.publish(t.a, xb, pitch, d, kk);
+            }
+            if (timing) {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+                tm[kTimePublish] += t1 - t0;
+                t0 = t1;
+            }
             ++epoch;
             exchange_point(flags, me, d, base + epoch, err, spin_limit);
+            if (timing) {
+                const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+                tm[kTimeWait] += t1 - t0;
+                t0 = t1;
+            }
             exchanged = true;
-            t.load_ghost(t.a, xb, pitch, d, kk);
+            asm volatile("" : "+s"(kx));
+            if constexpr (kStagedHere) {
+                if (staged) {
+                    const StageMap m = ring_map(d, kx);
+                    t.template stage_copy<false>(xb, pitch, m);
+                    __syncthreads();
+                    if (timing) {
+                        const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+                        tm[kTimeStageIn] += t1 - t0;
+                        t0 = t1;
+                    }
+                    t.template stage_cells<true>(t.a, m);
+                } else {
+                    t.load_ghost(t.a, xb, pitch, d, kk);
+                }
+            } else {
+                t.load_ghost(t.a, xb, pitch, d, kk);
+            }
+            // Set b = a.  Only cells a step never writes (outside the grid,
+            // for COLMASK / ROWCHECK tiles) keep their value in b, and there
+            // a and b agree; so b is dead from the last step of a segment to
+            // here, which leaves its registers free for the staged exchange.
+            if constexpr (kStagedHere) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) t.b[r][c] = t.a[r][c];
+            }
+            if (timing) {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+                tm[kTimeGhost] += t1 - t0;
+                tm[kTimeExchanges] += 1;
+                t0 = t1;
+            }
             if (poison) t.poison(t.a, d, kk, rows, P.cols);
+        }
+    }
+    if (timing) {
+        __syncthreads();
+        const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+        tm[kTimeSteps] += t1 - t0;
+        tm[kTimeTotal] += t1 - t_start;
+        if (threadIdx.x == 0) {
+            uint64_t* out = P.timing + (size_t)me * kTimingSlots;
+            for (int i = 0; i < kTimingSlots; ++i) atomicAdd((unsigned long long*)(out + i), (unsigned long long)tm[i]);
         }
     }
     // Neighbours read their initial ghost ring from the source grid; when the
@@ -378,7 +712,8 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
 // the stored region to dst.  SWEEP: src/dst are the sweep's HBM buffers, read
 // and written with device-scope accesses (other XCDs wrote / will read them
 // inside the same launch).
-template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS, bool SWEEP>
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS, bool SWEEP,
+          bool STAGED = true>
 __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int64_t steps,
                                             int me, uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
                                             uint32_t spin_limit, char* lds)
@@ -390,6 +725,7 @@ __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, 
     const int64_t pitch = P.pitch;
     const int rows = P.rows, cols = P.cols;
     t.edge = (T*)lds;
+    t.stage = (T*)lds + G::kEdgeElems + G::kHaloElems;
     T* hx = (T*)lds + G::kEdgeElems;  // [0, ER): w*hW, [ER, 2ER): e*hE, [2ER, 3ER): 0
     t.wave = uniform(threadIdx.x >> 6);
     t.lane = threadIdx.x & 63;
@@ -453,7 +789,7 @@ __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, 
     t.hbe = hx + (t.lane == 63 ? G::ER : 2 * G::ER);
     t.hbwe = hx + (t.lane == 0 ? 0 : (t.lane == 63 ? G::ER : 2 * G::ER));
 
-    run_epochs<HALO_ROWS>(t, P, d, steps, me, flags, base, epoch, err, spin_limit);
+    run_epochs<HALO_ROWS, STAGED>(t, P, d, steps, me, flags, base, epoch, err, spin_limit);
     t.template store_owned<SWEEP>(t.a, dst, pitch, d);
 }
 
@@ -639,11 +975,13 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
     T* grid = (T*)P.grid;
     if (!J.sweep) {
         const WgDesc& d = table[J.table_off + local];
+        // Batched jobs exchange lane by lane: the batched kernel holds every variant in one
+        // function, and the staging code would push it into register spills.
         if (halo_varies<T, C, R, WAVES, COLMASK>(P, d))
-            run_segment<T, C, R, WAVES, FMA, COLMASK, true, true, false>(P, d, grid, grid, P.T, me, flags, base,
+            run_segment<T, C, R, WAVES, FMA, COLMASK, true, true, false, false>(P, d, grid, grid, P.T, me, flags, base,
                                                                           epoch, err, spin_limit, lds);
         else
-            run_segment<T, C, R, WAVES, FMA, COLMASK, true, false, false>(P, d, grid, grid, P.T, me, flags, base,
+            run_segment<T, C, R, WAVES, FMA, COLMASK, true, false, false, false>(P, d, grid, grid, P.T, me, flags, base,
                                                                            epoch, err, spin_limit, lds);
         return;
     }
@@ -677,10 +1015,10 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
                 const int64_t per = (steps + P.k - 1) / P.k - 1;
                 epoch += per > 0 ? (uint32_t)per : 1u;
             } else if (halo_varies<T, C, R, WAVES, COLMASK>(P, d)) {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, true, true, true>(P, d, A, B, steps, me, flags, base,
+                run_segment<T, C, R, WAVES, FMA, COLMASK, true, true, true, false>(P, d, A, B, steps, me, flags, base,
                                                                              epoch, err, spin_limit, lds);
             } else {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, true, false, true>(P, d, A, B, steps, me, flags, base,
+                run_segment<T, C, R, WAVES, FMA, COLMASK, true, false, true, false>(P, d, A, B, steps, me, flags, base,
                                                                               epoch, err, spin_limit, lds);
             }
             ++epoch;

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdtb.so")
 
 F64, F32 = 0, 1
-DEBUG_TINY_SPIN, DEBUG_POISON = 1, 2
+DEBUG_TINY_SPIN, DEBUG_POISON, DEBUG_TIMING, DEBUG_DIRECT_XCHG = 1, 2, 4, 8
 PATH_AUTO, PATH_STEP, PATH_RESIDENT, PATH_SWEEP = 0, 1, 2, 3
 STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID_ARG", -2: "DTB_ERR_UNSUPPORTED", -3: "DTB_ERR_NOT_CORESIDENT",
           -4: "DTB_ERR_OUT_OF_MEMORY", -5: "DTB_ERR_HIP", -6: "DTB_ERR_TIMEOUT", -7: "DTB_ERR_NOT_PLANNED",
@@ -54,7 +54,7 @@ class Problem(ctypes.Structure):
 # Every symbol include/dtb.h and include/dtb_testing.h declare.
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
            "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep",
-           "dtb_batch_check", "dtb_test_batch")
+           "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing")
 TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
@@ -91,6 +91,8 @@ def load():
     lib.dtb_test_layout.restype = ctypes.c_int32
     lib.dtb_test_layout.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    lib.dtb_plan_timing.restype = ctypes.c_int
+    lib.dtb_plan_timing.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, P]
     lib.dtb_batch_check.restype = ctypes.c_int
     lib.dtb_batch_check.argtypes = [P]
     I64P, I32P = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
@@ -169,6 +171,23 @@ class Plan:
 
     def check(self, stream=None):
         _check(load().dtb_plan_check(self._h, _stream(stream)), "dtb_plan_check")
+
+    def timing(self, stream=None):
+        """Per-workgroup phase clocks (DTB_DEBUG_TIMING plans): list of dicts, times in microseconds."""
+        n = self.describe()["workgroups"]
+        buf = (ctypes.c_uint64 * (8 * n))()
+        _check(load().dtb_plan_timing(self._h, buf, 8 * n, _stream(stream)), "dtb_plan_timing")
+        names = ("steps", "publish", "wait", "ghost")
+        out = []
+        for i in range(n):
+            v = buf[8 * i:8 * i + 8]
+            d = {k: v[j] / 100.0 for j, k in enumerate(names)}  # 100 MHz ticks -> us
+            d["exchanges"] = int(v[4])
+            d["total"] = v[5] / 100.0
+            d["stage_out"] = v[6] / 100.0
+            d["stage_in"] = v[7] / 100.0
+            out.append(d)
+        return out
 
     def describe(self) -> dict:
         vals = (ctypes.c_int64 * len(DESCRIBE_FIELDS))()

@@ -76,7 +76,7 @@ def test_exact_f64_bitwise(shape, R):
 
 @pytest.mark.parametrize("shape", [(1, 1), (40, 1), (2, 300), (131, 127), (256, 256), (90, 520)],
                          ids=lambda s: f"{s[0]}x{s[1]}")
-@pytest.mark.parametrize("R", [8, 24])
+@pytest.mark.parametrize("R", [8, 16, 24])
 def test_exact_f32_bitwise(shape, R):
     rows, cols = shape
     rng = np.random.default_rng(rows * 7 + cols + R)
@@ -84,8 +84,14 @@ def test_exact_f32_bitwise(shape, R):
     u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(np.float32)
     for k, T in [(2, 5), (6, 40), (8, 200)]:
         _say("exact f32", rows, cols, "R", R, "k", k, "T", T)
-        got, _ = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_RESIDENT, ghost_k=k,
-                           rows_per_lane=R, exact=True)
+        try:
+            got, _ = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_RESIDENT, ghost_k=k,
+                               rows_per_lane=R, exact=True)
+        except dtb.DtbError as e:
+            # The resident FP32 kernels with 24 rows per lane spill registers, and the planner
+            # never picks a spilling kernel (the sweep instances and R = 8, 16 do not spill).
+            assert e.status == -3 and R == 24, (rows, cols, R, k, e)
+            continue
         ref = oracle.j2d5pt_f32(u, coeffs, T)
         assert np.array_equal(got, ref), (rows, cols, R, k, T)
 
@@ -464,3 +470,53 @@ def test_tuned_plan_is_correct():
     got, desc = _run_plan(u, coeffs, T, tune=True)
     print(f"[result] tuned plan {desc}")
     assert oracle.rel_max_err(got, oracle.j2d5pt_f64(u, coeffs, T)) <= TOL_F64
+
+
+def test_phase_clocks_do_not_change_results():
+    rows, cols, T, k = 500, 700, 60, 6
+    coeffs = inputs.dirichlet_weights(31)
+    u = inputs.uniform_grid(rows, cols, 32)
+    _say("phase clocks", rows, cols, "T", T, "k", k)
+    g = _dev(u)
+    plan = dtb.plan_for(g, T, path=dtb.PATH_RESIDENT, ghost_k=k, exact=True, debug=dtb.DEBUG_TIMING)
+    plan.run(g, coeffs, T)
+    plan.check()
+    clocks = plan.timing()
+    assert np.array_equal(g.cpu().numpy(), oracle.j2d5pt_f64(u, coeffs, T))
+    assert len(clocks) == plan.describe()["workgroups"]
+    for c in clocks:
+        assert c["exchanges"] == (T + k - 1) // k - 1
+        parts = c["steps"] + c["publish"] + c["wait"] + c["ghost"] + c["stage_out"] + c["stage_in"]
+        assert abs(c["total"] - parts) < 1e-6
+    assert all(v == 0 for c in plan.timing() for v in c.values())  # reading resets them
+    plan.destroy()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_staged_and_direct_exchange_agree(dtype):
+    # Border strips move through the LDS staging area unless the frames are too
+    # large for it; the lane-by-lane path is forced with DEBUG_DIRECT_XCHG.  Both
+    # must reproduce the oracle bit for bit, tiny tiles (frames without a hole)
+    # and the resident / sweep paths included.
+    npd = np.float64 if dtype == "f64" else np.float32
+    ref_fn = oracle.j2d5pt_f64 if dtype == "f64" else oracle.j2d5pt_f32
+    rng = np.random.default_rng(41)
+    coeffs = inputs.dirichlet_weights(rng)
+    cases = [((300, 260), dict(path=dtb.PATH_RESIDENT, ghost_k=1, rows_per_lane=8)),
+             ((300, 260), dict(path=dtb.PATH_RESIDENT, ghost_k=7, rows_per_lane=8)),
+             ((517, 389), dict(path=dtb.PATH_RESIDENT, ghost_k=12)),
+             ((517, 389), dict(path=dtb.PATH_RESIDENT, ghost_k=16)),
+             ((100, 3000), dict(path=dtb.PATH_RESIDENT, ghost_k=5, max_wg=40)),
+             ((700, 650), dict(path=dtb.PATH_SWEEP, ghost_k=6, depth_D=16, max_wg=6))]
+    for (rows, cols), opts in cases:
+        u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(npd)
+        T = 3 * opts["ghost_k"] + 2
+        ref = ref_fn(u, coeffs, T)
+        for debug in (0, dtb.DEBUG_DIRECT_XCHG):
+            _say("staged/direct", dtype, rows, cols, opts, "debug", debug, "T", T)
+            try:
+                got, _ = _run_plan(u, coeffs, T, dtype=npd, exact=True, debug=debug, **opts)
+            except dtb.DtbError as e:
+                assert e.status == -3, e  # this tiling does not fit on the chip at this precision
+                continue
+            assert np.array_equal(got, ref), (rows, cols, opts, debug)
