@@ -122,7 +122,7 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
 {
     double best = 1e300;
     bool found = false;
-    const int ks_auto[] = {4, 6, 8, 10, 12, 16};
+    const int ks_auto[] = {4, 6, 8, 10, 12, 16, 20, 24};
     std::vector<int> ks;
     if (o.ghost_k > 0) ks.push_back(o.ghost_k);
     else ks.assign(std::begin(ks_auto), std::end(ks_auto));
@@ -143,7 +143,7 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
             int cap = occ * n_cu;
             if (o.max_wg > 0) cap = std::min(cap, o.max_wg);
             if (L.nwg > cap) continue;
-            const double cost = layout_cost(L, occ, n_cu, 1.0);
+            const double cost = layout_cost(L, occ, n_cu, dtype == DTB_F64 ? 8 : 4);
             if (cost < best) {
                 best = cost;
                 *best_layout = L;
@@ -163,9 +163,10 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
 // of the computed region, store of the valid part) once per D steps.
 double sweep_step_us(const SweepPlan& sp, int dtype)
 {
-    const double instr_per_cell = 5.0 + 4.0 / sp.C;
-    const double t_step = (double)sp.ER * sp.EC * instr_per_cell / (64.0 * 2400.0) * 1.5;  // 64 lanes/clk/CU, 2.4 GHz, 1.5x slack
-    const double t_exch = 3.0, t_bar = 5.0;
+    const int eb = dtype == DTB_F64 ? 8 : 4;
+    const double t_step = tile_step_time_us(sp.ER, sp.EC, eb);
+    const double t_exch = exchange_time_us(sp.ER, sp.EC, sp.R, sp.C, eb, exchange_staged(sp.R, sp.C, eb, sp.k));
+    const double t_bar = 5.0;
     const double hbm_bytes_per_us = 4.0e6;
     const double b = dtype == DTB_F64 ? 8.0 : 4.0;
     double total = 0;
@@ -289,7 +290,7 @@ std::vector<std::pair<double, TuneChoice>> tune_candidates(int64_t rows, int64_t
         if (o.rows_per_lane > 0 && o.rows_per_lane != R) continue;
         int C = 0, waves = 0;
         if (!dtb_kernel(dtype, R, fma, false, false, &C, &waves)) continue;
-        for (int k : {2, 4, 6, 8, 10, 12, 16}) {
+        for (int k : {2, 4, 6, 8, 10, 12, 16, 20, 24}) {
             if (o.ghost_k > 0 && o.ghost_k != k) continue;
             if (o.path == DTB_PATH_AUTO || o.path == DTB_PATH_RESIDENT) {
                 Layout L;
@@ -302,7 +303,7 @@ std::vector<std::pair<double, TuneChoice>> tune_candidates(int64_t rows, int64_t
                         int cap = occ * n_cu;
                         if (o.max_wg > 0) cap = std::min(cap, o.max_wg);
                         if (L.nwg <= cap)
-                            out.push_back({layout_cost(L, occ, n_cu, 1.0) / (64.0 * 2400.0) * 7.0,
+                            out.push_back({layout_cost(L, occ, n_cu, dtype == DTB_F64 ? 8 : 4),
                                            TuneChoice{DTB_PATH_RESIDENT, R, k, 0}});
                     }
                 }

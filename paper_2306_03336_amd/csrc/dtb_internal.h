@@ -11,6 +11,17 @@ namespace dtb {
 constexpr int kWaveSize = 64;
 constexpr int kMaxNeighbours = 24;
 
+// Border strips go through the LDS staging area when the tile's two
+// register sets leave room for the staging code (at most 192 VGPRs per lane)
+// and the ring is at most stage_k(R) deep; otherwise lane by lane.  Shared by
+// the kernels (which size the area) and the planner (which prices it).
+constexpr int stage_k(int R) { return R >= 16 ? 12 : 8; }
+constexpr bool tile_stages(int R, int C, int elem_bytes) { return 2 * R * C * elem_bytes / 4 <= 192; }
+constexpr bool exchange_staged(int R, int C, int elem_bytes, int k)
+{
+    return tile_stages(R, C, elem_bytes) && k <= stage_k(R);
+}
+
 // Epoch flags live kFlagStride uint32 apart (4 KiB): every flag in its own
 // cache line and, whatever the channel interleave, spread over the HBM
 // channels, so polling workgroups do not queue on one channel.

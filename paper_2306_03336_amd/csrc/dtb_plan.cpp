@@ -194,13 +194,34 @@ bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st
     return true;
 }
 
-double layout_cost(const Layout& L, int slots_per_cu, int n_cu, double sync_steps)
+// Fitted to per-workgroup phase clocks at 2048^2 (FP64) and 1536^2 / 3072^2
+// (FP32): a step costs about 54 ps per FP64 cell and 39 ps per FP32 cell
+// (VALU-bound: wave64 FP64 and FP32 instructions at 16 and 32 lanes per
+// clock per SIMD) plus the per-step barrier; an exchange costs a few
+// microseconds of fixed latency (store completion, flag round trip, load
+// latency) plus a part that grows with the number of border cells moved
+// lane by lane.
+double tile_step_time_us(int ER, int EC, int elem_bytes)
+{
+    const double per_cell = elem_bytes == 8 ? 54e-6 : 39e-6;
+    return (double)ER * EC * per_cell + 0.11;
+}
+
+double exchange_time_us(int ER, int EC, int R, int C, int elem_bytes, bool staged)
+{
+    (void)elem_bytes;
+    if (staged) return 3.3 + 0.25e-3 * ER * EC * (elem_bytes == 8 ? 1.0 : 0.5);
+    return 4.0 + 0.15 * R * C;
+}
+
+double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes)
 {
     const int slots = std::max(1, slots_per_cu) * std::max(1, n_cu);
     if (L.nwg > slots) return 1e300;
     const int per_cu = (L.nwg + n_cu - 1) / n_cu;
-    const double cells = (double)per_cu * L.ER * L.EC;
-    return cells * (1.0 + sync_steps / L.k);
+    const bool staged = exchange_staged(L.R, L.C, elem_bytes, L.k);
+    return per_cu * tile_step_time_us(L.ER, L.EC, elem_bytes) +
+           exchange_time_us(L.ER, L.EC, L.R, L.C, elem_bytes, staged) / L.k;
 }
 
 // Even split of [1, len + 1) into n ranges.
@@ -295,13 +316,10 @@ bool plan_sweep(int64_t rows, int64_t cols, int R, int C, int waves, int k, int 
     return true;
 }
 
-double tile_step_us(int ER, int EC, int C, int active_rows)
+double tile_step_us(int ER, int EC, int elem_bytes, int active_rows)
 {
-    const double rows = std::min(ER, std::max(active_rows, 1));
-    const double instr_per_cell = 5.0 + 4.0 / C;
-    // 64 FP64/FP32 lanes per clock per CU at 2.4 GHz, with 1.5x slack for
-    // the barrier and LDS traffic of each step, plus a fixed 0.3 us.
-    return rows * EC * instr_per_cell / (64.0 * 2400.0) * 1.5 + 0.3;
+    const int rows = std::min(ER, std::max(active_rows, 1));
+    return tile_step_time_us(rows, EC, elem_bytes);
 }
 
 bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves, int nslots, BatchPlan* out)
@@ -309,7 +327,7 @@ bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves
     if (nslots < 1 || waves < 1) return false;
     BatchPlan bp;
     bp.nslots = nslots;
-    const double t_exch = 3.0, t_bar = 5.0;
+    const double t_bar = 5.0;  // device-wide barrier between sweep rounds
     std::vector<BatchJob> jobs;
     std::vector<std::vector<WgDesc>> tables;
     int flag_base = 0;
@@ -317,6 +335,9 @@ bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves
         const BatchSpec& q = probs[p];
         const int R = q.dtype == 0 ? r64 : r32, C = q.dtype == 0 ? 2 : 4;
         const int ER = waves * R, EC = kWaveSize * C;
+        const int eb = q.dtype == 0 ? 8 : 4;
+        // Batched jobs exchange lane by lane.
+        const double t_exch = exchange_time_us(ER, EC, R, C, eb, false);
         BatchJob J;
         J.prob = p;
         J.narrow_cols = q.cols < EC;
@@ -333,7 +354,7 @@ bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves
                 J.k = k;
                 J.D = (int)std::min<int64_t>(q.T, INT32_MAX);
                 const int act = (int)std::min<int64_t>(q.rows, ER);
-                J.dur = q.T * tile_step_us(ER, EC, C, act) + (double)q.T / k * t_exch;
+                J.dur = q.T * tile_step_us(ER, EC, eb, act) + (double)q.T / k * t_exch;
                 tab = L.wgs;
                 ok = true;
                 break;
@@ -346,7 +367,7 @@ bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves
                     SweepPlan sp;
                     if (!plan_sweep(q.rows, q.cols, R, C, waves, k, D, nslots, 1, &sp)) continue;
                     const int64_t nrounds = (q.T + D - 1) / D;
-                    const double per_tile = D * tile_step_us(ER, EC, C, ER) + (double)D / k * t_exch + t_bar;
+                    const double per_tile = D * tile_step_us(ER, EC, eb, ER) + (double)D / k * t_exch + t_bar;
                     const double dur = nrounds * per_tile * sp.tiles.size();
                     if (dur < best) {
                         best = dur;

@@ -62,10 +62,18 @@ bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st
 // The whole interior as computed and stored region.
 inline Region interior(int64_t rows, int64_t cols) { return Region{1, (int)rows + 1, 1, (int)cols + 1}; }
 
-// Static cost estimate of one step of a layout on a device with `slots`
-// co-resident workgroup slots: cells each compute unit advances per step,
-// times a factor for the exchange every k steps.
-double layout_cost(const Layout& L, int slots_per_cu, int n_cu, double sync_steps);
+// Time model (microseconds), calibrated on MI355X with one workgroup per
+// compute unit: one time step of an ER x EC register tile, and one exchange
+// (publish, flag wait, ghost load) of such a tile, through the LDS staging
+// area or lane by lane.
+double tile_step_time_us(int ER, int EC, int elem_bytes);
+double exchange_time_us(int ER, int EC, int R, int C, int elem_bytes, bool staged);
+
+// Model time of one step of a resident layout on n_cu compute units holding
+// slots_per_cu workgroups each: the compute units with the most tiles run
+// all their steps, and one exchange every k steps (the exchanges of
+// co-resident tiles overlap).  Infinite if the layout does not fit.
+double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes);
 
 // ---- tile-serial sweep
 
@@ -113,8 +121,8 @@ struct BatchPlan {
 };
 
 // Model time (us) of one step of a register tile of ER x EC cells of which
-// `active_rows` rows hold grid rows.
-double tile_step_us(int ER, int EC, int C, int active_rows);
+// `active_rows` rows hold grid rows (rows outside the grid are skipped).
+double tile_step_us(int ER, int EC, int elem_bytes, int active_rows);
 
 // Plan a batch: every problem becomes a job on a group of workgroups (held
 // on chip if it fits nslots tiles, else swept through big tiles), the jobs

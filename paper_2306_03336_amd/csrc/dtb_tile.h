@@ -135,10 +135,8 @@ struct Geo {
     // the direct per-lane path): a block of up to 2 * kStageK full-width rows
     // (EC cells each) and a block of ER side rows (kSide left cells, then
     // kSide right cells each).
-    // Tiles whose two register sets take more than 192 VGPRs per lane have
-    // no room for the staging code and always exchange lane by lane.
-    static constexpr bool kStaged = 2 * R * C * (int)sizeof(T) / 4 <= 192;
-    static constexpr int kStageK = R >= 16 ? 12 : 8;
+    static constexpr bool kStaged = tile_stages(R, C, (int)sizeof(T));
+    static constexpr int kStageK = stage_k(R);
     static constexpr int kSide = kStageK <= 8 ? 8 : 16;
     static constexpr int kStageRows = 2 * kStageK * EC;
     static constexpr int kStageElems = kStaged ? kStageRows + ER * 2 * kSide : 0;
