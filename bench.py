@@ -37,6 +37,42 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_UPDATE = 9
 
+# HBM traffic of k_dtb per launch, measured with rocprofv3 --pmc (FETCH_SIZE,
+# WRITE_SIZE, scaled by the same counters on a plain copy of known size); the
+# figure is reported only while the kernel sources hash to the value recorded
+# beside it.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dtb_j2d5pt_2048x2048_f64_T10000_traffic.md")
+
+
+def _kernel_source_hash() -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2306_03336_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def _recorded_traffic(workload: str):
+    """(bytes per launch, source hash) recorded for this workload, if the sources still match."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("workload") != workload or vals.get("kernel_source_sha256") != _kernel_source_hash():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
 
 def _cpu_baseline(w, budget_s: float):
     """Time the CPU oracle on a bounded number of steps of the same grid."""
@@ -80,10 +116,20 @@ def _one_config(dtb, inputs, torch, np, stream, name, T=None, warm=50):
     ms = _time_run(plan, g, w.coeffs, T, torch, stream)
     d = plan.describe()
     plan.destroy()
+    # The one-step-per-launch kernel on the same grid and step count.
+    sp = dtb.plan_for(g, T, path=dtb.PATH_STEP)
+    sp.run(g, w.coeffs, min(warm, T))
+    torch.cuda.synchronize()
+    sms = _time_run(sp, g, w.coeffs, T, torch, stream)
+    sp.destroy()
     del g
     torch.cuda.empty_cache()
-    return {"workload": name, "dtype": w.dtype, "T_timed": T, "ms": round(ms, 3),
-            "GCells_per_s": round(w.rows * w.cols * T / (ms / 1e3) / 1e9, 2), "plan": d}
+    gc = w.rows * w.cols * T / (ms / 1e3) / 1e9
+    sgc = w.rows * w.cols * T / (sms / 1e3) / 1e9
+    b = 8 if w.dtype == "f64" else 4
+    return {"workload": name, "dtype": w.dtype, "T_timed": T, "ms": round(ms, 3), "GCells_per_s": round(gc, 2),
+            "step_kernel_GCells_per_s": round(sgc, 2), "dtb_speedup": round(gc / sgc, 3),
+            "frac_of_untiled_hbm_roofline": round(gc / (PEAK_HBM_GBS / (2 * b)), 3), "plan": d}
 
 
 def _batched(dtb, inputs, torch, np, stream):
@@ -144,7 +190,14 @@ def main() -> int:
     ap.add_argument("--no-step-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary configurations")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed region, copy a buffer of this many MiB three times with an "
+                         "elementwise kernel (a plain copy of known size, to scale hardware byte counters)")
+    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     args = ap.parse_args()
+    if args.source_hash:
+        print(_kernel_source_hash())
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is described in DESIGN.md but not built)", file=sys.stderr)
@@ -208,10 +261,30 @@ def main() -> int:
                 "achieved_GBs_algorithmic": round(bval * bytes_per_update, 1)}
         sp.destroy()
 
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)  # an elementwise kernel: reads and writes the buffer once each
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: 3 copies of {args.copy_probe_mb} MiB", file=sys.stderr, flush=True)
+        del a, b
+
+    b = 8 if w.dtype == "f64" else 4
+    # Context figures: the untiled kernel's HBM roofline (one read and one write
+    # per cell-step) and the LDS roofline at one LDS read and write per
+    # cell-step (128 B per clock per CU); the DTB kernel keeps its tile in
+    # registers and is bound by neither.
+    hbm_roof = PEAK_HBM_GBS / (2 * b)
+    lds_roof = 256 * 2.4e9 * 128 / (2 * b) / 1e9
+    context = {"untiled_hbm_roofline_GCells": hbm_roof, "frac_of_untiled_hbm_roofline": round(value / hbm_roof, 3),
+               "lds_roofline_GCells": round(lds_roof, 1), "frac_of_lds_roofline": round(value / lds_roof, 3)}
+
     peak = PEAK_FP64_VECTOR_TFLOPS if w.dtype == "f64" else PEAK_FP32_VECTOR_TFLOPS
     achieved = FLOPS_PER_UPDATE * updates / (avg_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4), "traffic": _recorded_traffic(w.name),
             "kernel": "k_dtb", "avg_launch_ms": round(avg_ms, 4)}
 
     extras = {}
@@ -236,6 +309,7 @@ def main() -> int:
         "config": {"workload": w.name, "rows": w.rows, "cols": w.cols, "T": w.T, "halo": w.halo,
                    "weights": w.weights, "seed": w.seed, "plan": desc},
         "roofline": roof,
+        "context": context,
         "baseline_1step": base,
         "cpu_baseline": cpu,
         "other_configs": extras,
@@ -246,4 +320,6 @@ def main() -> int:
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    rc = main()
+    if rc:
+        sys.exit(rc)
