@@ -76,7 +76,9 @@ typedef struct {
     int32_t path;        /* dtb_path */
     int32_t ghost_k;     /* steps between inter-workgroup halo exchanges (ghost ring depth); 0 = auto */
     int32_t depth_D;     /* sweep: steps per round (temporal depth of a big tile); 0 = auto */
-    int32_t rows_per_lane; /* register tile height per lane (instantiated sizes only); 0 = auto */
+    int32_t rows_per_lane; /* register tile height per lane; 0 = auto.  Instantiated: FP64 8, 16, 24
+                              (2 columns per lane) and 12 (4 columns per lane); FP32 8, 16, 24, 28
+                              (4 columns per lane).  Tiles are 8 waves x rows_per_lane rows high. */
     int32_t max_wg;      /* cap on workgroups; 0 = every compute unit */
     int32_t exact;       /* 1: separately rounded products, plain left-to-right sum (bitwise CPU parity) */
     int32_t debug_flags; /* DTB_DEBUG_* bits; 0 in production */

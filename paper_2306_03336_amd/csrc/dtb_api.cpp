@@ -25,7 +25,8 @@ namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // bounded wait: a few seconds of polling
 constexpr int kNumXcd = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
-constexpr int kDtbRowsPerLane[] = {8, 16, 24, 28};  // instantiated: FP64 8, 16, 24; FP32 8, 16, 24, 28
+// Instantiated rows per lane: FP64 8, 16, 24 (2 columns per lane) and 12 (4 columns); FP32 8, 16, 24, 28.
+constexpr int kDtbRowsPerLane[] = {8, 12, 16, 24, 28};
 
 struct DeviceInfo {
     int device = -1;

@@ -15,7 +15,7 @@ constexpr int kMaxNeighbours = 24;
 // register sets leave room for the staging code (at most 192 VGPRs per lane)
 // and the ring is at most stage_k(R) deep; otherwise lane by lane.  Shared by
 // the kernels (which size the area) and the planner (which prices it).
-constexpr int stage_k(int R) { return R >= 16 ? 12 : 8; }
+constexpr int stage_k(int R) { return R >= 12 ? 12 : 8; }
 constexpr bool tile_stages(int R, int C, int elem_bytes) { return 2 * R * C * elem_bytes / 4 <= 192; }
 constexpr bool exchange_staged(int R, int C, int elem_bytes, int k)
 {

@@ -150,9 +150,10 @@ hipError_t launch_copy_halo(int dtype, const void* src, void* dst, int64_t pitch
 }
 
 // Instantiated DTB kernels (one translation unit each, dtb_inst_*.hip): FP64
-// with 2 columns per lane, FP32 with 4 (16 bytes of a row per lane either
-// way), 8 waves per workgroup, R rows per lane.
+// with 2 columns per lane (R = 8, 16, 24) or 4 (R = 12), FP32 with 4, 8 waves
+// per workgroup, R rows per lane.
 #define DTB_DECLARE(NAME) const void* NAME(bool sweep, bool fma, bool colmask, bool rowcheck);
+DTB_DECLARE(pick_f64c4_r12)
 DTB_DECLARE(pick_f64_r8)
 DTB_DECLARE(pick_f64_r16)
 DTB_DECLARE(pick_f64_r24)
@@ -172,6 +173,7 @@ static const void* dtb_kernel_any(bool sweep, int dtype, int R, bool fma, bool c
         case 8: return pick_f64_r8(sweep, fma, colmask, rowcheck);
         case 16: return pick_f64_r16(sweep, fma, colmask, rowcheck);
         case 24: return pick_f64_r24(sweep, fma, colmask, rowcheck);
+        case 12: *C = 4; return pick_f64c4_r12(sweep, fma, colmask, rowcheck);
         default: return nullptr;
         }
     } else {

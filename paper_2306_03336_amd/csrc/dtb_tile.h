@@ -81,6 +81,28 @@ __device__ __forceinline__ T wave_shl1(T v)
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Per-lane choice without a branch: lanes whose bit is set in `mask` (a
+// wave-wide lane mask) get v, the others keep x.  Written as v_cndmask so the
+// compiler cannot turn it into a branch around the instruction producing v
+// (which for an LDS load would then wait on every one).
+__device__ __forceinline__ uint32_t lane_pick32(uint64_t mask, uint32_t x, uint32_t v)
+{
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(v), "s"(mask));
+    return r;
+}
+__device__ __forceinline__ float lane_pick(uint64_t mask, float x, float v)
+{
+    return __builtin_bit_cast(float, lane_pick32(mask, __builtin_bit_cast(uint32_t, x), __builtin_bit_cast(uint32_t, v)));
+}
+__device__ __forceinline__ double lane_pick(uint64_t mask, double x, double v)
+{
+    const uint64_t xb = __builtin_bit_cast(uint64_t, x), vb = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = lane_pick32(mask, (uint32_t)xb, (uint32_t)vb);
+    const uint32_t hi = lane_pick32(mask, (uint32_t)(xb >> 32), (uint32_t)(vb >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Wrap-safe "counter a has reached b".
 __device__ __forceinline__ bool reached(uint32_t a, uint32_t b) { return (int32_t)(a - b) >= 0; }
 
@@ -352,17 +374,19 @@ struct Tile {
         if constexpr (!LOAD) __builtin_amdgcn_s_waitcnt(0x0F70);  // as in publish: no wait per LDS store
         const int spare = G::kStageElems + lane;
         const int lslot = lane * C;
-        // Per column slot: in the map's full-row columns (nm = -1), a side
-        // column (wm = -1, side slot weoff).  Masks rather than bools: the
-        // selects below are then plain bit operations on values.
-        int nm[C], wm[C], weoff[C];
+        // Per column slot (once per call): the lanes whose column is one of
+        // the map's full-row columns (nmask) or side columns (wmask), as
+        // wave-wide masks, and the side slot of each lane (its spare slot
+        // when it has none).
+        uint64_t nmask[C], wmask[C];
+        int sslot[C];  // side slot; 0 for a lane without one (a load there is harmless, a store is not)
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int col = lcol0 + c;
-            nm[c] = (col >= m.c0 && col < m.c1) ? -1 : 0;
             const bool w = col >= m.w0 && col < m.w1, e = col >= m.e0 && col < m.e1;
-            wm[c] = (w || e) ? -1 : 0;
-            weoff[c] = w ? col - m.w0 : kSide + col - m.e0;
+            nmask[c] = __builtin_amdgcn_ballot_w64(col >= m.c0 && col < m.c1);
+            wmask[c] = __builtin_amdgcn_ballot_w64(w || e);
+            sslot[c] = w ? col - m.w0 : (e ? kSide + col - m.e0 : 0);
         }
         // Row r of this wave: bit 31 set for a full row (low bits: its first
         // slot), a side row's first slot, or -1 when the row moves nothing.
@@ -376,30 +400,52 @@ struct Tile {
                     : in_m ? G::kStageRows + (g - m.m0) * 2 * kSide
                            : -1;
         }
+        // Row kinds are uniform, so each row takes one branch: a full row is
+        // one address per lane (the C cells at fixed offsets), a side row one
+        // address per cell (the side slot, or the spare).  Loads go in groups
+        // of four rows, all issued before any result is picked into the tile.
+        constexpr int kGroup = 4;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int info = __builtin_amdgcn_readlane(rowinfo, r);
-            const int fm = (info < 0 && info != -1) ? -1 : 0;  // full row
-            const int sm = info >= 0 ? -1 : 0;                 // side row
-            const int base = info & 0x7fffffff;
+        for (int r0 = 0; r0 < R; r0 += kGroup) {
+            T v[kGroup][C];
+            uint64_t pick[kGroup][C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                // A lane moves the cell when the row is full and the column is
-                // in the map's columns, or the row is a side row and the
-                // column a side column.
-                const int sw = sm & wm[c];
-                const bool live = ((fm & nm[c]) | sw) != 0;
-                const int slot = (fm & (base + lslot + c)) | (~fm & ((sw & (base + weoff[c])) | (~sw & spare)));
-                if constexpr (LOAD) {
-                    const T v = stage[slot];
-                    x[r][c] = live ? v : x[r][c];
+            for (int rr = 0; rr < kGroup && r0 + rr < R; ++rr) {
+                const int r = r0 + rr;
+                const int info = __builtin_amdgcn_readlane(rowinfo, r);
+#pragma unroll
+                for (int c = 0; c < C; ++c) pick[rr][c] = 0;
+                if (info == -1) continue;
+                if (info < 0) {
+                    T* const p = stage + (info & 0x7fffffff) + lslot;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        if constexpr (LOAD) {
+                            v[rr][c] = p[c];
+                            pick[rr][c] = nmask[c];
+                        } else {
+                            p[c] = x[r][c];
+                        }
+                    }
                 } else {
-                    stage[slot] = x[r][c];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        if constexpr (LOAD) {
+                            v[rr][c] = stage[info + sslot[c]];
+                            pick[rr][c] = wmask[c];
+                        } else {
+                            const int idx = (int)lane_pick32(wmask[c], (uint32_t)spare, (uint32_t)(info + sslot[c]));
+                            stage[idx] = x[r][c];
+                        }
+                    }
                 }
             }
-            // Groups of four rows: enough accesses in flight to cover the LDS
-            // latency without holding a register pair per cell.
-            if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (LOAD) {
+#pragma unroll
+                for (int rr = 0; rr < kGroup && r0 + rr < R; ++rr)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) x[r0 + rr][c] = lane_pick(pick[rr][c], x[r0 + rr][c], v[rr][c]);
+            }
         }
     }
 

@@ -51,8 +51,12 @@ def _run_plan(u, coeffs, T, dtype=np.float64, cols=None, **opts):
 SHAPES = [(1, 1), (1, 37), (45, 1), (3, 200), (127, 131), (256, 256), (200, 300), (70, 130), (129, 257)]
 
 
+# FP64 register tiles (rows x columns) by rows per lane: 2 columns per lane, or 4 at R = 12.
+F64_TILE = {8: (64, 128), 12: (96, 256), 16: (128, 128), 24: (192, 128)}
+
+
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
-@pytest.mark.parametrize("R", [8, 16, 24])
+@pytest.mark.parametrize("R", [8, 12, 16, 24])
 def test_exact_f64_bitwise(shape, R):
     rows, cols = shape
     rng = np.random.default_rng(rows * 1000 + cols + R)
@@ -65,9 +69,10 @@ def test_exact_f64_bitwise(shape, R):
         try:
             got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_RESIDENT, ghost_k=k, rows_per_lane=R, exact=True)
         except dtb.DtbError as e:
-            # Only the largest tile may be unavailable: its exact variant for grids narrower than the
-            # tile spills registers, and the planner never picks a spilling kernel.
-            assert e.status == -3 and R == 24 and (rows < 192 or cols < 128), (rows, cols, R, k, e)
+            # Only the largest tiles may be unavailable: their exact variants for grids narrower than
+            # the tile spill registers, and the planner never picks a spilling kernel.
+            er, ec = F64_TILE[R]
+            assert e.status == -3 and R in (12, 24) and (rows < er or cols < ec), (rows, cols, R, k, e)
             continue
         ref = oracle.j2d5pt_f64(u, coeffs, T)
         assert desc["path"] == dtb.PATH_RESIDENT and desc["exact"] == 1
