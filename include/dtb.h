@@ -85,6 +85,9 @@ typedef struct {
     int32_t tune;        /* 1: time the best few candidate tilings on a scratch grid and keep the fastest
                             (results cached per shape/precision/device, and in the text file named by the
                             environment variable DTB_TUNE_CACHE if set); 0: static cost model only */
+    int32_t waves;       /* waves per workgroup of the resident path: 8, or 4 (FP64, 24 rows per lane:
+                            half-height tiles, two workgroups per compute unit so that one's exchange
+                            overlaps the other's steps); 0 = choose */
 } dtb_plan_opts;
 
 /* Debug bits for dtb_plan_opts.debug_flags. */
@@ -176,7 +179,7 @@ dtb_status dtb_plan_timing(dtb_plan_t plan, uint64_t* out, int32_t n, void* stre
 /*
  * Describe a plan: fills up to `n` int64 values in this order: path,
  * workgroups, ghost_k, depth_D, ext_rows, ext_cols, tiles_rows, tiles_cols,
- * rows_per_lane, cols_per_lane, big_tiles, exact.  Returns DTB_OK.
+ * rows_per_lane, cols_per_lane, big_tiles, exact, waves.  Returns DTB_OK.
  */
 dtb_status dtb_plan_describe(dtb_plan_t plan, int64_t* values, int32_t n);
 

@@ -154,6 +154,7 @@ hipError_t launch_copy_halo(int dtype, const void* src, void* dst, int64_t pitch
 // per workgroup, R rows per lane.
 #define DTB_DECLARE(NAME) const void* NAME(bool sweep, bool fma, bool colmask, bool rowcheck);
 DTB_DECLARE(pick_f64c4_r12)
+DTB_DECLARE(pick_f64w4_r24)
 DTB_DECLARE(pick_f64_r8)
 DTB_DECLARE(pick_f64_r16)
 DTB_DECLARE(pick_f64_r24)
@@ -163,9 +164,17 @@ DTB_DECLARE(pick_f32_r24)
 DTB_DECLARE(pick_f32_r28)
 #undef DTB_DECLARE
 
-static const void* dtb_kernel_any(bool sweep, int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C,
-                                  int* waves)
+static const void* dtb_kernel_any(bool sweep, int dtype, int R, int want_waves, bool fma, bool colmask,
+                                  bool rowcheck, int* C, int* waves)
 {
+    if (want_waves == 4) {
+        // Half-height workgroups, two per compute unit (resident path only).
+        *waves = 4;
+        *C = 2;
+        if (!sweep && dtype == 0 && R == 24) return pick_f64w4_r24(sweep, fma, colmask, rowcheck);
+        return nullptr;
+    }
+    if (want_waves != 0 && want_waves != 8) return nullptr;
     *waves = 8;
     if (dtype == 0) {
         *C = 2;
@@ -188,14 +197,14 @@ static const void* dtb_kernel_any(bool sweep, int dtype, int R, bool fma, bool c
     }
 }
 
-const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
+const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves, int want_waves)
 {
-    return dtb_kernel_any(false, dtype, R, fma, colmask, rowcheck, C, waves);
+    return dtb_kernel_any(false, dtype, R, want_waves, fma, colmask, rowcheck, C, waves);
 }
 
 const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
 {
-    return dtb_kernel_any(true, dtype, R, fma, colmask, rowcheck, C, waves);
+    return dtb_kernel_any(true, dtype, R, 8, fma, colmask, rowcheck, C, waves);
 }
 
 hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st)

@@ -14,8 +14,10 @@ hipError_t launch_copy_halo(int dtype, const void* src, void* dst, int64_t pitch
 
 // The DTB kernel for (dtype, rows per lane R, variant), or nullptr when that R
 // is not instantiated.  *C receives the columns per lane and *waves the waves
-// per workgroup of the instance.
-const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves);
+// per workgroup of the instance.  want_waves: 0 or 8 for the standard
+// 8-wave workgroups, 4 for the half-height instances (FP64 R = 24 only).
+const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves,
+                       int want_waves = 0);
 
 // The tile-serial sweep kernel of the same instance (arguments: ProbDesc,
 // SweepArgs, descriptor table, flags, error word, spin limit).

@@ -220,8 +220,13 @@ double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes)
     if (L.nwg > slots) return 1e300;
     const int per_cu = (L.nwg + n_cu - 1) / n_cu;
     const bool staged = exchange_staged(L.R, L.C, elem_bytes, L.k);
-    return per_cu * tile_step_time_us(L.ER, L.EC, elem_bytes) +
-           exchange_time_us(L.ER, L.EC, L.R, L.C, elem_bytes, staged) / L.k;
+    const double step = tile_step_time_us(L.ER, L.EC, elem_bytes);
+    const double exch = exchange_time_us(L.ER, L.EC, L.R, L.C, elem_bytes, staged) / L.k;
+    if (per_cu <= 1) return step + exch;
+    // Several workgroups per compute unit: measured (2048^2 FP64, two
+    // half-height workgroups per unit), their exchanges hardly overlap the
+    // other workgroup's steps and each takes about 1.5x longer than alone.
+    return per_cu * step + 1.5 * exch;
 }
 
 // Even split of [1, len + 1) into n ranges.

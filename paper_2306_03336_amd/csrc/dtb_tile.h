@@ -868,7 +868,7 @@ __device__ __forceinline__ char* dtb_lds()
 }
 
 template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
-__global__ __launch_bounds__(WAVES * 64) void k_dtb(ProbDesc P, const WgDesc* __restrict__ wgs,
+__global__ __launch_bounds__(WAVES * 64, 2) void k_dtb(ProbDesc P, const WgDesc* __restrict__ wgs,
                                                     uint32_t* flags, int* err, uint32_t spin_limit)
 {
     const int me = blockIdx.x;
@@ -937,7 +937,7 @@ __device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err
 // its valid part to buffer B; a device-wide barrier separates tiles.  Round r
 // reads bufs[r & 1] and writes bufs[(r + 1) & 1]; bufs[0] is the grid.
 template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
-__global__ __launch_bounds__(WAVES * 64) void k_dtb_sweep(ProbDesc P, SweepArgs S, const WgDesc* __restrict__ table,
+__global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepArgs S, const WgDesc* __restrict__ table,
                                                           uint32_t* flags, int* err, uint32_t spin_limit)
 {
     const int me = blockIdx.x;
@@ -1116,12 +1116,12 @@ __global__ __launch_bounds__(kDtbWaves * 64) void k_dtb_batched(const ProbDesc* 
 }
 
 // The 2 x 8 kernels (resident / sweep x fma, colmask, rowcheck) of one
-// (precision, columns per lane, rows per lane) instance.
-template <typename T, int C, int R>
+// (precision, columns per lane, rows per lane, waves) instance.
+template <typename T, int C, int R, int WAVES = kDtbWaves>
 const void* pick_instance(bool sweep, bool fma, bool colmask, bool rowcheck)
 {
-#define DTB_K(F, M, W) (sweep ? (const void*)&k_dtb_sweep<T, C, R, kDtbWaves, F, M, W> \
-                              : (const void*)&k_dtb<T, C, R, kDtbWaves, F, M, W>)
+#define DTB_K(F, M, W) (sweep ? (const void*)&k_dtb_sweep<T, C, R, WAVES, F, M, W> \
+                              : (const void*)&k_dtb<T, C, R, WAVES, F, M, W>)
     const int v = (fma ? 4 : 0) | (colmask ? 2 : 0) | (rowcheck ? 1 : 0);
     switch (v) {
     case 0: return DTB_K(false, false, false);

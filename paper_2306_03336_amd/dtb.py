@@ -24,7 +24,7 @@ STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID_ARG", -2: "DTB_ERR_UNSUPPORTED", -3:
           -4: "DTB_ERR_OUT_OF_MEMORY", -5: "DTB_ERR_HIP", -6: "DTB_ERR_TIMEOUT", -7: "DTB_ERR_NOT_PLANNED",
           -8: "DTB_ERR_MISMATCH"}
 DESCRIBE_FIELDS = ("path", "workgroups", "ghost_k", "depth_D", "ext_rows", "ext_cols", "tiles_rows",
-                   "tiles_cols", "rows_per_lane", "cols_per_lane", "big_tiles", "exact")
+                   "tiles_cols", "rows_per_lane", "cols_per_lane", "big_tiles", "exact", "waves")
 TEST_MAX_NEIGHBOURS = 24
 TEST_LAYOUT_STRIDE = 8 + TEST_MAX_NEIGHBOURS
 
@@ -43,7 +43,7 @@ class Grid(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("ghost_k", ctypes.c_int32), ("depth_D", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("max_wg", ctypes.c_int32), ("exact", ctypes.c_int32),
-                ("debug_flags", ctypes.c_int32), ("tune", ctypes.c_int32)]
+                ("debug_flags", ctypes.c_int32), ("tune", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -157,10 +157,11 @@ class Plan:
 
     def __init__(self, rows: int, cols: int, pitch: int, dtype: int, T_hint: int = 0, path: int = PATH_AUTO,
                  ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0, exact: bool = False,
-                 tune: bool = False, debug: int = 0):
+                 tune: bool = False, debug: int = 0, waves: int = 0):
         lib = load()
         self._h = ctypes.c_void_p()
-        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, debug, 1 if tune else 0)
+        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, debug, 1 if tune else 0,
+                        waves)
         _check(lib.dtb_plan(ctypes.byref(self._h), rows, cols, pitch, dtype, T_hint, ctypes.byref(opts)), "dtb_plan")
         self.rows, self.cols, self.pitch, self.dtype = rows, cols, pitch, dtype
 

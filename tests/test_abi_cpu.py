@@ -50,7 +50,7 @@ def test_plan_rejects_bad_shape(args):
 
 def test_plan_rejects_null_out_and_bad_options():
     assert _plan_rc(5, 5, 7, 0, out=False) == -1
-    for field, value in [("path", 9), ("ghost_k", -1), ("exact", 2), ("debug_flags", 16), ("max_wg", -3), ("tune", 2)]:
+    for field, value in [("path", 9), ("ghost_k", -1), ("exact", 2), ("debug_flags", 16), ("max_wg", -3), ("tune", 2), ("waves", 6)]:
         o = dtb.PlanOpts()
         setattr(o, field, value)
         assert _plan_rc(5, 5, 7, 0, o) == -1, field

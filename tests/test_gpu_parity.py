@@ -525,3 +525,18 @@ def test_staged_and_direct_exchange_agree(dtype):
                 assert e.status == -3, e  # this tiling does not fit on the chip at this precision
                 continue
             assert np.array_equal(got, ref), (rows, cols, opts, debug)
+
+
+@pytest.mark.parametrize("shape", [(150, 300), (517, 389), (2048, 700)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_half_height_workgroups_bitwise(shape):
+    # FP64, 24 rows per lane, 4 waves per workgroup (two workgroups per compute unit).
+    rows, cols = shape
+    rng = np.random.default_rng(rows + cols)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols)
+    for k, T in [(1, 3), (4, 21), (10, 45)]:
+        _say("half-height", rows, cols, "k", k, "T", T)
+        got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_RESIDENT, ghost_k=k, rows_per_lane=24, waves=4,
+                              exact=True)
+        assert desc["waves"] == 4 and desc["ext_rows"] == 96
+        assert np.array_equal(got, oracle.j2d5pt_f64(u, coeffs, T)), (rows, cols, k, T)
