@@ -250,6 +250,7 @@ struct Tile {
     template <bool HALO_ROWS>
     __device__ __forceinline__ void step(T (&src)[R][C], T (&dst)[R][C], int parity, int rows)
     {
+        static_assert(R >= 2, "a wave holds at least two rows");
         // Publish this wave's current top and bottom rows for the waves above and below.
         T* mytop = edge_row(parity, wave + 1, 0) + lane * C;
         T* mybot = edge_row(parity, wave + 1, 1) + lane * C;
@@ -258,8 +259,16 @@ struct Tile {
             mytop[c] = src[0][c];
             mybot[c] = src[R - 1][c];
         }
-        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);  // the stores issue first
+        // Rows 1 .. R-2 need only this wave's cells: the first half of them
+        // goes before the barrier (covering the LDS stores above), the
+        // second half after it (covering the loads of the neighbours' rows),
+        // and the first and last rows come last.
         T top[C], bot[C];
+        constexpr int kHalf = R / 2;
+#pragma unroll
+        for (int r = 1; r < kHalf; ++r) row<HALO_ROWS>(src, dst, r, top, bot, rows);
+        __syncthreads();
         const T* above = edge_row(parity, wave, 1) + lane * C;      // bottom row of the wave above
         const T* below = edge_row(parity, wave + 2, 0) + lane * C;  // top row of the wave below
 #pragma unroll
@@ -267,43 +276,53 @@ struct Tile {
             top[c] = above[c];
             bot[c] = below[c];
         }
+        __builtin_amdgcn_sched_barrier(0);  // the loads issue before the rows that do not need them
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if constexpr (ROWCHECK) {
-                const int g = g0 + r;
-                if (g < 1 || g > rows) continue;
-            }
-            T rbw = bw, rbe = be, rbwe = bwe;
-            if constexpr (HALO_ROWS) {
-                rbw = hbw[wave * R + r];
-                rbe = hbe[wave * R + r];
-                rbwe = hbwe[wave * R + r];
-            }
-            const T wlane = wave_shr1(src[r][C - 1]);  // west neighbour of slot 0
-            const T elane = wave_shl1(src[r][0]);      // east neighbour of slot C-1
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const T Wv = (c == 0) ? wlane : src[r][c - 1];
-                const T Ev = (c == C - 1) ? elane : src[r][c + 1];
-                const T Sv = (r == 0) ? top[c] : src[r - 1][c];
-                const T Nv = (r == R - 1) ? bot[c] : src[r + 1][c];
-                T v;
-                if (c == 0 && c == C - 1)
-                    v = j2d5pt_edge<FMA, true, true>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
-                else if (c == 0)
-                    v = j2d5pt_edge<FMA, true, false>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
-                else if (c == C - 1)
-                    v = j2d5pt_edge<FMA, false, true>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
-                else
-                    v = j2d5pt_edge<FMA, false, false>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
-                if constexpr (COLMASK) v = colact[c] ? v : dst[r][c];
-                dst[r][c] = v;
-            }
-            // The row-by-row halo path is rare (edge tiles with a varying
-            // halo); keep the scheduler from hoisting every row's LDS reads,
-            // which would cost a register pair per row.
-            if constexpr (HALO_ROWS) __builtin_amdgcn_sched_barrier(0);
+        for (int r = kHalf; r < R - 1; ++r) row<HALO_ROWS>(src, dst, r, top, bot, rows);
+        row<HALO_ROWS>(src, dst, 0, top, bot, rows);
+        row<HALO_ROWS>(src, dst, R - 1, top, bot, rows);
+    }
+
+    // Row r of one step: src -> dst.  top / bot are the neighbouring waves'
+    // rows (read only by rows 0 and R-1).
+    template <bool HALO_ROWS>
+    __device__ __forceinline__ void row(T (&src)[R][C], T (&dst)[R][C], int r, const T (&top)[C], const T (&bot)[C],
+                                        int rows)
+    {
+        if constexpr (ROWCHECK) {
+            const int g = g0 + r;
+            if (g < 1 || g > rows) return;
         }
+        T rbw = bw, rbe = be, rbwe = bwe;
+        if constexpr (HALO_ROWS) {
+            rbw = hbw[wave * R + r];
+            rbe = hbe[wave * R + r];
+            rbwe = hbwe[wave * R + r];
+        }
+        const T wlane = wave_shr1(src[r][C - 1]);  // west neighbour of slot 0
+        const T elane = wave_shl1(src[r][0]);      // east neighbour of slot C-1
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const T Wv = (c == 0) ? wlane : src[r][c - 1];
+            const T Ev = (c == C - 1) ? elane : src[r][c + 1];
+            const T Sv = (r == 0) ? top[c] : src[r - 1][c];
+            const T Nv = (r == R - 1) ? bot[c] : src[r + 1][c];
+            T v;
+            if (c == 0 && c == C - 1)
+                v = j2d5pt_edge<FMA, true, true>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+            else if (c == 0)
+                v = j2d5pt_edge<FMA, true, false>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+            else if (c == C - 1)
+                v = j2d5pt_edge<FMA, false, true>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+            else
+                v = j2d5pt_edge<FMA, false, false>(Wv, Ev, Sv, src[r][c], Nv, rbw, rbe, rbwe, k);
+            if constexpr (COLMASK) v = colact[c] ? v : dst[r][c];
+            dst[r][c] = v;
+        }
+        // The row-by-row halo path is rare (edge tiles with a varying halo);
+        // keep the scheduler from hoisting every row's LDS reads, which would
+        // cost a register pair per row.
+        if constexpr (HALO_ROWS) __builtin_amdgcn_sched_barrier(0);
     }
 
     // The owned cells within k of an owned edge: what the neighbours need.
