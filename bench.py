@@ -85,9 +85,24 @@ def _cpu_baseline(w, budget_s: float):
         u = oracle.j2d5pt_f64(u, w.coeffs, chunk, nthreads=nt)
         steps += chunk
     dt = time.perf_counter() - t0
+    # One thread, a shorter sample of the same grid.
+    u1 = w.grid()
+    s1, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < budget_s / 4 and s1 < w.T:
+        u1 = oracle.j2d5pt_f64(u1, w.coeffs, 10, nthreads=1)
+        s1 += 10
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(w.rows * w.cols * steps / dt / 1e9, 4), "unit": "GCells/s", "cores": nt,
             "kind": "oracle",
-            "sample": f"{w.rows}x{w.cols} FP64, {steps} of the {w.T} time steps ({dt:.1f} s, FP64, {nt} threads)"}
+            "sample": f"{w.rows}x{w.cols} FP64, {steps} of the {w.T} time steps ({dt:.1f} s, FP64, {nt} threads)",
+            "one_thread_value": round(w.rows * w.cols * s1 / dt1 / 1e9, 4),
+            "one_thread_sample": f"{s1} steps ({dt1:.1f} s)", "host_cpu": model, "host_cpus": os.cpu_count()}
 
 
 def _time_run(plan, g, coeffs, T, torch, stream, reps=1):
@@ -194,6 +209,9 @@ def main() -> int:
                     help="after the timed region, copy a buffer of this many MiB three times with an "
                          "elementwise kernel (a plain copy of known size, to scale hardware byte counters)")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--phase-clocks", action="store_true",
+                    help="after the timed region, run the workload once more with per-workgroup phase clocks "
+                         "and report the time per step spent in steps and in each exchange phase")
     args = ap.parse_args()
     if args.source_hash:
         print(_kernel_source_hash())
@@ -252,10 +270,32 @@ def main() -> int:
         sp.run(g, w.coeffs, w.T)
         e1.record(stream)
         torch.cuda.synchronize()
-        bms = e0.elapsed_time(e1)
+        bms_launch = e0.elapsed_time(e1)
+        # The same T launches captured once in a HIP graph and replayed (no
+        # per-launch host overhead); the faster of the two is the baseline.
+        bms_graph = None
+        try:
+            side = torch.cuda.Stream()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(graph, stream=side):
+                    sp.run(g, w.coeffs, w.T, stream=side)
+            graph.replay()
+            torch.cuda.synchronize()
+            e0.record(stream)
+            graph.replay()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            bms_graph = e0.elapsed_time(e1)
+            del graph
+        except Exception as e:  # the launch-by-launch figure stands on its own
+            print(f"[bench] step-kernel graph skipped: {type(e).__name__}: {e}", file=sys.stderr, flush=True)
+        bms = min(bms_launch, bms_graph) if bms_graph is not None else bms_launch
         bval = updates / (bms / 1e3) / 1e9
         bytes_per_update = 2 * (8 if w.dtype == "f64" else 4)
         base = {"value": round(bval, 3), "unit": "GCells/s", "ms_per_run": round(bms, 3),
+                "ms_per_run_launches": round(bms_launch, 3),
+                "ms_per_run_graph": None if bms_graph is None else round(bms_graph, 3),
                 "launches": w.T, "dtb_speedup": round(value / bval, 3),
                 "hbm_roofline_GCells": PEAK_HBM_GBS / bytes_per_update,
                 "achieved_GBs_algorithmic": round(bval * bytes_per_update, 1)}
@@ -285,7 +325,23 @@ def main() -> int:
     achieved = FLOPS_PER_UPDATE * updates / (avg_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": _recorded_traffic(w.name),
-            "kernel": "k_dtb", "avg_launch_ms": round(avg_ms, 4)}
+            "kernel": "k_dtb", "avg_launch_ms": round(avg_ms, 4),
+            "launch_ms_min_median_max": [round(min(kern_ms), 4), round(float(np.median(kern_ms)), 4),
+                                         round(max(kern_ms), 4)]}
+
+    phases = None
+    if args.phase_clocks:
+        # Where a step's time goes, from per-workgroup phase clocks of the same plan shape.
+        tp = dtb.plan_for(g, w.T, debug=dtb.DEBUG_TIMING)
+        g.copy_(u0)
+        tp.run(g, w.coeffs, w.T)
+        tp.check()
+        clocks = tp.timing()
+        tp.destroy()
+        keys = ("steps", "stage_out", "publish", "wait", "stage_in", "ghost", "total")
+        phases = {k: round(float(np.mean([c[k] for c in clocks])) / w.T, 4) for k in keys}
+        phases["unit"] = "us per time step, mean over workgroups"
+        phases["exchanges"] = int(max(c["exchanges"] for c in clocks))
 
     extras = {}
     if not args.no_extras:
@@ -310,6 +366,7 @@ def main() -> int:
                    "weights": w.weights, "seed": w.seed, "plan": desc},
         "roofline": roof,
         "context": context,
+        "phase_clocks": phases,
         "baseline_1step": base,
         "cpu_baseline": cpu,
         "other_configs": extras,
