@@ -244,6 +244,16 @@ struct Tile {
         return edge + ((size_t)((parity * (WAVES + 2) + slot) * 2 + bottom)) * EC;
     }
 
+    // Position of (lane, column slot c) in an edge row: 16-byte groups, lane
+    // fastest, so that each 16-byte LDS access of a wave covers one
+    // contiguous kilobyte (no bank conflicts when a lane holds more than 16
+    // bytes of a row, as FP64 with 4 columns does).
+    static constexpr int kVec = 16 / (int)sizeof(T) < C ? 16 / (int)sizeof(T) : C;
+    __device__ __forceinline__ static int edge_pos(int ln, int c)
+    {
+        return ((c / kVec) * kWaveSize + ln) * kVec + c % kVec;
+    }
+
     // One time step: src -> dst.  `parity` selects the LDS edge buffer.
     // HALO_ROWS: the halo addends change from row to row (an edge tile of a
     // grid whose west/east halo is not constant) and are read from LDS.
@@ -252,12 +262,12 @@ struct Tile {
     {
         static_assert(R >= 2, "a wave holds at least two rows");
         // Publish this wave's current top and bottom rows for the waves above and below.
-        T* mytop = edge_row(parity, wave + 1, 0) + lane * C;
-        T* mybot = edge_row(parity, wave + 1, 1) + lane * C;
+        T* mytop = edge_row(parity, wave + 1, 0);
+        T* mybot = edge_row(parity, wave + 1, 1);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            mytop[c] = src[0][c];
-            mybot[c] = src[R - 1][c];
+            mytop[edge_pos(lane, c)] = src[0][c];
+            mybot[edge_pos(lane, c)] = src[R - 1][c];
         }
         __builtin_amdgcn_sched_barrier(0);  // the stores issue first
         // Rows 1 .. R-2 need only this wave's cells: the first half of them
@@ -269,12 +279,12 @@ struct Tile {
 #pragma unroll
         for (int r = 1; r < kHalf; ++r) row<HALO_ROWS>(src, dst, r, top, bot, rows);
         __syncthreads();
-        const T* above = edge_row(parity, wave, 1) + lane * C;      // bottom row of the wave above
-        const T* below = edge_row(parity, wave + 2, 0) + lane * C;  // top row of the wave below
+        const T* above = edge_row(parity, wave, 1);      // bottom row of the wave above
+        const T* below = edge_row(parity, wave + 2, 0);  // top row of the wave below
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            top[c] = above[c];
-            bot[c] = below[c];
+            top[c] = above[edge_pos(lane, c)];
+            bot[c] = below[edge_pos(lane, c)];
         }
         __builtin_amdgcn_sched_barrier(0);  // the loads issue before the rows that do not need them
 #pragma unroll
@@ -375,7 +385,8 @@ struct Tile {
 
     // Move this lane's cells of a stage map between registers and the
     // staging area (LOAD: stage -> registers).  A full row is stored as the
-    // whole tile row (slot = tile column), so every lane has a slot there;
+    // whole tile row (in the edge-row order, edge_pos), so every lane has a
+    // slot there;
     // side rows hold only the side columns, and a lane with nothing to move
     // in a side row uses a spare slot of its own past the staging area.
     // Branch-free: lane r works out the kind and first slot of row r, read
@@ -392,7 +403,6 @@ struct Tile {
         asm volatile("" : "+v"(lcol0));
         if constexpr (!LOAD) __builtin_amdgcn_s_waitcnt(0x0F70);  // as in publish: no wait per LDS store
         const int spare = G::kStageElems + lane;
-        const int lslot = lane * C;
         // Per column slot (once per call): the lanes whose column is one of
         // the map's full-row columns (nmask) or side columns (wmask), as
         // wave-wide masks, and the side slot of each lane (its spare slot
@@ -436,14 +446,14 @@ struct Tile {
                 for (int c = 0; c < C; ++c) pick[rr][c] = 0;
                 if (info == -1) continue;
                 if (info < 0) {
-                    T* const p = stage + (info & 0x7fffffff) + lslot;
+                    T* const p = stage + (info & 0x7fffffff);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         if constexpr (LOAD) {
-                            v[rr][c] = p[c];
+                            v[rr][c] = p[edge_pos(lane, c)];
                             pick[rr][c] = nmask[c];
                         } else {
-                            p[c] = x[r][c];
+                            p[edge_pos(lane, c)] = x[r][c];
                         }
                     }
                 } else {
@@ -491,7 +501,7 @@ struct Tile {
         const int rr = uniform(tid / EC);  // the same for the whole wave
         const bool cact = cc < m.c1 - m.c0;
         T* const fbase = xb + m.c0 + cc;
-        T* const fslot = stage + rr * EC + m.tc0 + cc;
+        T* const fslot = stage + rr * EC + edge_pos((m.tc0 + cc) / C, (m.tc0 + cc) % C);  // as in stage_cells
         const int sc = tid % SW, sr = tid / SW;
         const bool left = sc < kSide;
         const int scol = left ? m.w0 + sc : m.e0 + (sc - kSide);
@@ -824,9 +834,10 @@ __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, 
         const int col = d.ext_c0 + idx;
         const T vt = (col <= cols + 1) ? grid[(int64_t)gt * pitch + col] : T(0);
         const T vb = (gb <= rows + 1 && col <= cols + 1) ? grid[(int64_t)gb * pitch + col] : T(0);
+        const int pos = Tl::edge_pos(idx / C, idx % C);
         for (int p = 0; p < 2; ++p) {
-            t.edge_row(p, 0, 1)[idx] = vt;
-            t.edge_row(p, WAVES + 1, 0)[idx] = vb;
+            t.edge_row(p, 0, 1)[pos] = vt;
+            t.edge_row(p, WAVES + 1, 0)[pos] = vb;
         }
     }
     // West/east halo products for the rows of an edge tile (zero elsewhere:
