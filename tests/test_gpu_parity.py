@@ -542,7 +542,9 @@ def test_staged_and_direct_exchange_agree(dtype):
              ((517, 389), dict(path=dtb.PATH_RESIDENT, ghost_k=12)),
              ((517, 389), dict(path=dtb.PATH_RESIDENT, ghost_k=16)),
              ((100, 3000), dict(path=dtb.PATH_RESIDENT, ghost_k=5, max_wg=40)),
-             ((700, 650), dict(path=dtb.PATH_SWEEP, ghost_k=6, depth_D=16, max_wg=6))]
+             ((700, 650), dict(path=dtb.PATH_SWEEP, ghost_k=6, depth_D=16, max_wg=6)),
+             ((450, 900), dict(path=dtb.PATH_RESIDENT, ghost_k=9, rows_per_lane=12)),
+             ((450, 900), dict(path=dtb.PATH_RESIDENT, ghost_k=11, rows_per_lane=24, waves=4))]
     for (rows, cols), opts in cases:
         u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(npd)
         T = 3 * opts["ghost_k"] + 2
