@@ -218,7 +218,7 @@ def main() -> int:
         return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described in DESIGN.md but not built)", file=sys.stderr)
+              "(a multi-GPU layout is not implemented)", file=sys.stderr)
         return 2
 
     import numpy as np

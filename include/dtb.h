@@ -46,7 +46,7 @@ typedef enum { DTB_F64 = 0, DTB_F32 = 1 } dtb_dtype;
 typedef enum {
     DTB_OK = 0,
     DTB_ERR_INVALID_ARG = -1,    /* a NULL pointer, rows/cols < 1, pitch < cols+2, T < 0, bad dtype/option */
-    DTB_ERR_UNSUPPORTED = -2,    /* shape or option this build does not handle */
+    DTB_ERR_UNSUPPORTED = -2,    /* shape or option the library does not handle */
     DTB_ERR_NOT_CORESIDENT = -3, /* the plan needs more workgroups than can run at once */
     DTB_ERR_OUT_OF_MEMORY = -4,  /* workspace allocation failed */
     DTB_ERR_HIP = -5,            /* a HIP runtime call or kernel launch failed */
