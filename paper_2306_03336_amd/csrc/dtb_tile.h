@@ -333,6 +333,11 @@ struct Tile {
         // keep the scheduler from hoisting every row's LDS reads, which would
         // cost a register pair per row.
         if constexpr (HALO_ROWS) __builtin_amdgcn_sched_barrier(0);
+        // Tall FP32 tiles (more than 16 rows of 4 columns) leave no registers
+        // for the scheduler to run ahead over many rows: fence it every four.
+        if constexpr (sizeof(T) == 4 && R > 16) {
+            if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
     }
 
     // The owned cells within k of an owned edge: what the neighbours need.
@@ -340,6 +345,9 @@ struct Tile {
     // without an L2 write-back.
     __device__ __forceinline__ void publish(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk)
     {
+        // An opaque copy of the pitch: the per-row offsets are not hoisted out
+        // of the epoch loop (where they would hold registers through the steps).
+        asm volatile("" : "+v"(pitch));
         // Every store below sits in its own exec-masked block, so the
         // compiler's wait-count tracking cannot see that the tile registers
         // are no longer the target of an outstanding load (the paths into the
@@ -366,6 +374,7 @@ struct Tile {
     // computed region, not owned) with device-scope (sc1) loads.
     __device__ __forceinline__ void load_ghost(T (&x)[R][C], T* xb, int64_t pitch, const WgDesc& d, int kk)
     {
+        asm volatile("" : "+v"(pitch));  // as in publish
         const int r_lo = max(d.own_r0 - kk, d.cr_r0), r_hi = min(d.own_r1 + kk, d.cr_r1);
         const int c_lo = max(d.own_c0 - kk, d.cr_c0), c_hi = min(d.own_c1 + kk, d.cr_c1);
 #pragma unroll
@@ -496,6 +505,7 @@ struct Tile {
         static_assert(kThreads % EC == 0 && kThreads % SW == 0 && EC % kWaveSize == 0, "staging copy shape");
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));  // as in stage_cells: no hoisting out of the epoch loop
+        asm volatile("" : "+v"(pitch));
         const int nn = m.n1 - m.n0, nrows = nn + (m.s1 - m.s0);
         const int cc = tid % EC;
         const int rr = uniform(tid / EC);  // the same for the whole wave
