@@ -341,8 +341,6 @@ bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves
         const int R = q.dtype == 0 ? r64 : r32, C = q.dtype == 0 ? 2 : 4;
         const int ER = waves * R, EC = kWaveSize * C;
         const int eb = q.dtype == 0 ? 8 : 4;
-        // Batched jobs exchange lane by lane.
-        const double t_exch = exchange_time_us(ER, EC, R, C, eb, false);
         BatchJob J;
         J.prob = p;
         J.narrow_cols = q.cols < EC;
@@ -359,6 +357,7 @@ bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves
                 J.k = k;
                 J.D = (int)std::min<int64_t>(q.T, INT32_MAX);
                 const int act = (int)std::min<int64_t>(q.rows, ER);
+                const double t_exch = exchange_time_us(ER, EC, R, C, eb, exchange_staged(R, C, eb, k));
                 J.dur = q.T * tile_step_us(ER, EC, eb, act) + (double)q.T / k * t_exch;
                 tab = L.wgs;
                 ok = true;
@@ -372,6 +371,7 @@ bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves
                     SweepPlan sp;
                     if (!plan_sweep(q.rows, q.cols, R, C, waves, k, D, nslots, 1, &sp)) continue;
                     const int64_t nrounds = (q.T + D - 1) / D;
+                    const double t_exch = exchange_time_us(ER, EC, R, C, eb, exchange_staged(R, C, eb, k));
                     const double per_tile = D * tile_step_us(ER, EC, eb, ER) + (double)D / k * t_exch + t_bar;
                     const double dur = nrounds * per_tile * sp.tiles.size();
                     if (dur < best) {
