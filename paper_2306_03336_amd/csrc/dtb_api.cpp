@@ -133,10 +133,13 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
 {
     double best = 1e300;
     bool found = false;
-    const int ks_auto[] = {4, 6, 8, 10, 12, 16, 20, 24};
+    // Every ring depth from 2 to 24: with all tiles running side by side, the
+    // deepest ring whose tiles still fit on the chip usually wins (2048^2 FP64:
+    // k = 11 fits 252 tiles of 96 x 256, k = 12 would need 261).
     std::vector<int> ks;
     if (o.ghost_k > 0) ks.push_back(o.ghost_k);
-    else ks.assign(std::begin(ks_auto), std::end(ks_auto));
+    else
+        for (int k = 2; k <= 24; ++k) ks.push_back(k);
     for (int R : kDtbRowsPerLane) {
         if (o.rows_per_lane > 0 && o.rows_per_lane != R) continue;
         // Half-height workgroups only on request: measured slower than full
