@@ -223,6 +223,9 @@ struct Tile {
     using G = Geo<T, C, R, WAVES>;
     static constexpr int ER = G::ER;
     static constexpr int EC = G::EC;
+    // Some cells are never written by a step (those outside the grid).
+    static constexpr bool kKeepsCells = COLMASK || ROWCHECK;
+    using LdsT = __attribute__((address_space(3))) T;  // a cell addressed by its LDS byte address
 
     T a[R][C];
     T b[R][C];
@@ -416,15 +419,23 @@ struct Tile {
         // the map's full-row columns (nmask) or side columns (wmask), as
         // wave-wide masks, and the side slot of each lane (its spare slot
         // when it has none).
+        // A side row's cell c sits at the LDS byte address sbyte[c] +
+        // sinc[c] * (the row's first slot): its side slot for a lane that has
+        // one (sinc = the cell size), else the lane's spare slot (sinc 0; a
+        // load there is harmless, a store must not land in a live slot).
+        // One 24-bit multiply-add per cell (slots are far below 2^24).
+        const uint32_t stage_lds = (uint32_t)(uintptr_t)stage;  // low half of an LDS pointer: its LDS address
         uint64_t nmask[C], wmask[C];
-        int sslot[C];  // side slot; 0 for a lane without one (a load there is harmless, a store is not)
+        uint32_t sbyte[C], sinc[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int col = lcol0 + c;
             const bool w = col >= m.w0 && col < m.w1, e = col >= m.e0 && col < m.e1;
             nmask[c] = __builtin_amdgcn_ballot_w64(col >= m.c0 && col < m.c1);
             wmask[c] = __builtin_amdgcn_ballot_w64(w || e);
-            sslot[c] = w ? col - m.w0 : (e ? kSide + col - m.e0 : 0);
+            const int slot = w ? col - m.w0 : (e ? kSide + col - m.e0 : spare);
+            sbyte[c] = stage_lds + (uint32_t)slot * (uint32_t)sizeof(T);
+            sinc[c] = (w || e) ? (uint32_t)sizeof(T) : 0u;
         }
         // Row r of this wave: bit 31 set for a full row (low bits: its first
         // slot), a side row's first slot, or -1 when the row moves nothing.
@@ -468,12 +479,14 @@ struct Tile {
                 } else {
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
+                        uint32_t addr;
+                        asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(addr) : "s"(info), "v"(sinc[c]), "v"(sbyte[c]));
+                        LdsT* const p = (LdsT*)addr;
                         if constexpr (LOAD) {
-                            v[rr][c] = stage[info + sslot[c]];
+                            v[rr][c] = *p;
                             pick[rr][c] = wmask[c];
                         } else {
-                            const int idx = (int)lane_pick32(wmask[c], (uint32_t)spare, (uint32_t)(info + sslot[c]));
-                            stage[idx] = x[r][c];
+                            *p = x[r][c];
                         }
                     }
                 }
@@ -755,7 +768,8 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
             // for COLMASK / ROWCHECK tiles) keep their value in b, and there
             // a and b agree; so b is dead from the last step of a segment to
             // here, which leaves its registers free for the staged exchange.
-            if constexpr (kStagedHere) {
+            // A tile whose steps write every cell needs no copy at all.
+            if constexpr (kStagedHere && Tile_::kKeepsCells) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
 #pragma unroll
