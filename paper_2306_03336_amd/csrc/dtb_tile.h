@@ -421,9 +421,11 @@ struct Tile {
         // when it has none).
         // A side row's cell c sits at the LDS byte address sbyte[c] +
         // sinc[c] * (the row's first slot): its side slot for a lane that has
-        // one (sinc = the cell size), else the lane's spare slot (sinc 0; a
-        // load there is harmless, a store must not land in a live slot).
-        // One 24-bit multiply-add per cell (slots are far below 2^24).
+        // one.  A lane without one loads the row's first slot (the same
+        // address for all such lanes: a broadcast, no bank conflict; the
+        // value is not picked) and stores to its own spare slot (sinc 0: a
+        // store must not land in a live slot).  One 24-bit multiply-add per
+        // cell (slots are far below 2^24).
         const uint32_t stage_lds = (uint32_t)(uintptr_t)stage;  // low half of an LDS pointer: its LDS address
         uint64_t nmask[C], wmask[C];
         uint32_t sbyte[C], sinc[C];
@@ -433,9 +435,9 @@ struct Tile {
             const bool w = col >= m.w0 && col < m.w1, e = col >= m.e0 && col < m.e1;
             nmask[c] = __builtin_amdgcn_ballot_w64(col >= m.c0 && col < m.c1);
             wmask[c] = __builtin_amdgcn_ballot_w64(w || e);
-            const int slot = w ? col - m.w0 : (e ? kSide + col - m.e0 : spare);
+            const int slot = w ? col - m.w0 : (e ? kSide + col - m.e0 : (LOAD ? 0 : spare));
             sbyte[c] = stage_lds + (uint32_t)slot * (uint32_t)sizeof(T);
-            sinc[c] = (w || e) ? (uint32_t)sizeof(T) : 0u;
+            sinc[c] = (w || e || LOAD) ? (uint32_t)sizeof(T) : 0u;
         }
         // Row r of this wave: bit 31 set for a full row (low bits: its first
         // slot), a side row's first slot, or -1 when the row moves nothing.
