@@ -273,12 +273,17 @@ struct Tile {
             mybot[edge_pos(lane, c)] = src[R - 1][c];
         }
         __builtin_amdgcn_sched_barrier(0);  // the stores issue first
-        // Rows 1 .. R-2 need only this wave's cells: the first half of them
-        // goes before the barrier (covering the LDS stores above), the
-        // second half after it (covering the loads of the neighbours' rows),
-        // and the first and last rows come last.
+        // Rows 1 .. R-2 need only this wave's cells: the first ones go
+        // before the barrier (covering the LDS stores above), the rest after
+        // it (covering the loads of the neighbours' rows), and the first and
+        // last rows come last.
         T top[C], bot[C];
-        constexpr int kHalf = R / 2;
+        // Inner rows [1, kHalf) go before the barrier.  Measured: the 12-row
+        // tile (FP64, 4 columns) is fastest with just one row there (an early
+        // barrier lets less wave skew build up in front of it; 2195 -> 2213
+        // GCells/s at 2048^2), the 24-row tiles with half of their rows
+        // (one row there costs them 1 %).
+        constexpr int kHalf = R == 12 ? 2 : R / 2;
 #pragma unroll
         for (int r = 1; r < kHalf; ++r) row<HALO_ROWS>(src, dst, r, top, bot, rows);
         __syncthreads();
