@@ -2,24 +2,31 @@
 """Benchmark: j2d5pt under deep temporal blocking on one MI355X.
 
 One "step" of this benchmark is one whole pass of the hot path over one
-batch: dtb_run of the 2048 x 2048 FP64 grid for T = 10000 time steps (the
-grid stays on chip for all of them).  Throughput is counted in interior
-cell-updates: rows * cols * T per step, divided by wall time.
+batch: dtb_run of the 16384 x 16384 FP64 grid for T = 2000 time steps (the
+largest single-GPU FP64 configuration; the grid is larger than the chip, so the
+tile-serial sweep runs it).  Throughput is counted in interior cell-updates:
+rows * cols * T per step, divided by wall time.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--no-step-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--no-extras]
 
 Prints ONE JSON line.  Besides the headline value it carries:
-  roofline      the DTB kernel's achieved FP64 arithmetic rate (9 flops per
-                cell-update: one multiply and four fused multiply-adds)
-                against the chip's FP64 vector peak; duration from HIP events
-                on the launch stream;
-  baseline_1step  the untiled one-launch-per-time-step kernel on the same
-                grid (T launches, HBM/Infinity-Cache bound), and DTB's speedup;
-  cpu_baseline  the CPU oracle on a bounded sample of the same workload;
-  other_configs the FP32 precision pair (3072^2 resident, 16384^2 swept for
-                400 of its 2000 steps), the 8192^2 FP64 tile-serial sweep, and
-                the 64-grid batch in one graph-replayed launch against the
-                same grids run one at a time.
+  roofline        the DTB kernel's achieved FP64 arithmetic rate (9 flops per
+                  cell-update: one multiply and four fused multiply-adds) against
+                  the chip's FP64 vector peak; kernel duration from HIP events on
+                  the launch stream; HBM traffic per launch from rocprofv3
+                  counters while the kernel sources match the recorded hash;
+  denominators    measured on the running part: LDS read/write bandwidth, copy
+                  bandwidth from the Infinity Cache and from HBM, device-barrier
+                  and neighbour-flag latency;
+  baseline_1step  the untiled one-launch-per-time-step kernel on the same grid;
+  cpu_baseline    the CPU oracle on a bounded sample of the same workload;
+  other_configs   every other configuration at its full step count: median,
+                  min and max of >= 5 runs, the one-step kernel beside it, the
+                  error against the FP64 oracle recorded by the full-size parity
+                  tests on the same kernel sources, and the roofline fractions;
+                  and the 2048^2 and 8192^2 FP64 workloads under the three
+                  synchronisation designs (neighbour flags, a device-wide
+                  barrier per exchange, overlapped per-workgroup blocking).
 """
 from __future__ import annotations
 
@@ -33,32 +40,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X FP64 vector (FMA counted as 2 flops)
-PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # with packed FP32; the kernels are built without it (78.6 unpacked)
 PEAK_HBM_GBS = 8000.0
+PEAK_LDS_TBS = 256 * 2.4e9 * 128 / 1e12  # datasheet LDS rate, 128 B per clock per CU
 FLOPS_PER_UPDATE = 9
+HEADLINE = "j2d5pt_16384x16384_f64_T2000"
 
-# HBM traffic of k_dtb per launch, measured with rocprofv3 --pmc (FETCH_SIZE,
-# WRITE_SIZE, scaled by the same counters on a plain copy of known size); the
-# figure is reported only while the kernel sources hash to the value recorded
-# beside it.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dtb_j2d5pt_2048x2048_f64_T10000_traffic.md")
+# HBM traffic per launch of the headline kernel (rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE, each scaled by the same counter on a plain copy of known size)
+# and the full-size accuracy records (pytest with DTB_ACCURACY_LOG); both are
+# used only while the kernel sources hash to the value recorded with them.
+PROFILES = os.path.join(ROOT, "profiles")
+ACCURACY_FILE = os.path.join(PROFILES, "accuracy_fullsize.md")
 
 
-def _kernel_source_hash() -> str:
-    import hashlib
-    csrc = os.path.join(ROOT, "paper_2306_03336_amd", "csrc")
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()
+def _source_hash() -> str:
+    from paper_2306_03336_amd import build
+    return build.kernel_source_hash()
+
+
+def _traffic_file(workload: str) -> str:
+    return os.path.join(PROFILES, f"k_dtb_{workload[len('j2d5pt_'):]}_traffic.md")
 
 
 def _recorded_traffic(workload: str):
-    """(bytes per launch, source hash) recorded for this workload, if the sources still match."""
+    """Bytes per launch recorded for this workload, if the kernel sources still match."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(_traffic_file(workload)).read()
     except OSError:
         return None
     vals = {}
@@ -66,7 +74,7 @@ def _recorded_traffic(workload: str):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("workload") != workload or vals.get("kernel_source_sha256") != _kernel_source_hash():
+    if vals.get("workload") != workload or vals.get("kernel_source_sha256") != _source_hash():
         return None
     try:
         return int(vals["traffic_bytes_per_launch"])
@@ -74,80 +82,176 @@ def _recorded_traffic(workload: str):
         return None
 
 
-def _cpu_baseline(w, budget_s: float):
-    """Time the CPU oracle on a bounded number of steps of the same grid."""
-    import oracle  # test infrastructure, used only for this leg
-    u = w.grid()
-    nt = oracle.default_threads()
-    steps, t0 = 0, time.perf_counter()
-    chunk = 50
-    while time.perf_counter() - t0 < budget_s and steps < w.T:
-        u = oracle.j2d5pt_f64(u, w.coeffs, chunk, nthreads=nt)
-        steps += chunk
-    dt = time.perf_counter() - t0
-    # One thread, a shorter sample of the same grid.
-    u1 = w.grid()
-    s1, t1 = 0, time.perf_counter()
-    while time.perf_counter() - t1 < budget_s / 4 and s1 < w.T:
-        u1 = oracle.j2d5pt_f64(u1, w.coeffs, 10, nthreads=1)
-        s1 += 10
-    dt1 = time.perf_counter() - t1
-    model = ""
+def _accuracy_records():
+    """Full-size accuracy records (JSON objects, one per bullet line) that match the current sources."""
     try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        text = open(ACCURACY_FILE).read()
     except OSError:
-        pass
-    return {"value": round(w.rows * w.cols * steps / dt / 1e9, 4), "unit": "GCells/s", "cores": nt,
-            "kind": "oracle",
-            "sample": f"{w.rows}x{w.cols} FP64, {steps} of the {w.T} time steps ({dt:.1f} s, FP64, {nt} threads)",
-            "one_thread_value": round(w.rows * w.cols * s1 / dt1 / 1e9, 4),
-            "one_thread_sample": f"{s1} steps ({dt1:.1f} s)", "host_cpu": model, "host_cpus": os.cpu_count()}
+        return []
+    h = _source_hash()
+    out = []
+    for line in text.splitlines():
+        line = line.strip()
+        if line.startswith("- `{") and line.endswith("}`"):
+            try:
+                rec = json.loads(line[3:-1])
+            except ValueError:
+                continue
+            if rec.get("kernel_source_sha256") == h:
+                out.append(rec)
+    return out
 
 
-def _time_run(plan, g, coeffs, T, torch, stream, reps=1):
-    """Best of `reps` runs of T steps, milliseconds (HIP events on the launch stream)."""
-    best = None
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+def _error_for(records, workload, dtype):
+    for r in records:
+        if r.get("workload") == workload and r.get("dtype") == dtype:
+            keep = {k: v for k, v in r.items() if k not in ("plan", "exact_mode_plan", "kernel_source_sha256")}
+            keep["source"] = "tests/test_gpu_fullsize.py / tests/test_gpu_parity.py, profiles/accuracy_fullsize.md"
+            return keep
+    return None
+
+
+def _stats(ms_list, updates):
+    import numpy as np
+    ms = sorted(ms_list)
+    med = float(np.median(ms))
+    return {"reps": len(ms), "median_ms": round(med, 4), "min_ms": round(ms[0], 4), "max_ms": round(ms[-1], 4),
+            "GCells_per_s": round(updates / (med / 1e3) / 1e9, 2),
+            "GCells_per_s_min_max": [round(updates / (ms[-1] / 1e3) / 1e9, 2), round(updates / (ms[0] / 1e3) / 1e9, 2)]}
+
+
+def _time_runs(run, torch, stream, reps):
+    """Durations (ms) of `reps` calls of run(), HIP events on the launch stream around each."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
         e0.record(stream)
-        plan.run(g, coeffs, T)
+        run()
         e1.record(stream)
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in ev]
+
+
+def _step_baseline(dtb, torch, stream, g, u0, coeffs, T, reps):
+    """The untiled kernel: T launches of k_step, timed as launches (once) and as a HIP graph of the T
+    launches (reps replays); the faster is the baseline."""
+    sp = dtb.plan_for(g, T, path=dtb.PATH_STEP)
+    g.copy_(u0)
+    sp.run(g, coeffs, min(T, 200))
+    torch.cuda.synchronize()
+    launches = _time_runs(lambda: sp.run(g, coeffs, T), torch, stream, 1)[0]
+    graph_ms = None
+    try:
+        side = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                sp.run(g, coeffs, T, stream=side)
+        graph.replay()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        best = ms if best is None else min(best, ms)
-    plan.check()
-    return best
+        graph_ms = _time_runs(graph.replay, torch, stream, reps)
+        del graph
+    except Exception as e:  # the launch-by-launch figure stands on its own
+        print(f"[bench] step-kernel graph skipped: {type(e).__name__}: {e}", file=sys.stderr, flush=True)
+    sp.destroy()
+    return launches, graph_ms
 
 
-def _one_config(dtb, inputs, torch, np, stream, name, T=None, warm=50):
+def _lds_bytes_per_launch(desc, T, b):
+    """LDS bytes a DTB launch moves, counted from the plan: every step each wave stores its top and bottom
+    rows and loads its neighbours' (4 rows of ext_cols cells); every exchange moves the border strips
+    (rim out, ring in) through the staging area, each cell written and read once (counted as 4 b per
+    ring-or-rim cell, rim + ring <= 4 k (ext_rows + ext_cols))."""
+    nwg, waves, ER, EC, k = desc["workgroups"], desc["waves"], desc["ext_rows"], desc["ext_cols"], desc["ghost_k"]
+    tiles = max(1, desc["big_tiles"])
+    per_step = nwg * waves * 4 * EC * b
+    per_exchange = nwg * 4 * k * (ER + EC) * 4 * b
+    # The sweep runs every big tile for all T steps (one after another), idle slots excluded only
+    # approximately (every slot of the launch counted): an upper bound.
+    return tiles * T * (per_step + per_exchange / max(k, 1))
+
+
+def _denominators(dtb):
+    """Measured: LDS bandwidth, copy bandwidth (MALL- and HBM-sized buffers), barrier and flag latency."""
+    out = {}
+    try:
+        ms, byt = dtb.probe(dtb.PROBE_LDS_READ, iters=4096)
+        out["lds_read_TBs"] = round(byt / (ms / 1e3) / 1e12, 2)
+        ms, byt = dtb.probe(dtb.PROBE_LDS_WRITE, iters=4096)
+        out["lds_write_TBs"] = round(byt / (ms / 1e3) / 1e12, 2)
+        for label, size, iters in (("copy_64MiB", 64 << 20, 50), ("copy_4GiB", 4 << 30, 5)):
+            ms, byt = dtb.probe(dtb.PROBE_COPY, size=size, iters=iters)
+            out[label + "_GBs"] = round(byt / (ms / 1e3) / 1e9, 1)
+        ms, n = dtb.probe(dtb.PROBE_BARRIER, iters=2000)
+        out["grid_barrier_us"] = round(ms * 1e3 / n, 3)
+        ms, n = dtb.probe(dtb.PROBE_FLAGS, iters=2000)
+        out["neighbour_flags_us"] = round(ms * 1e3 / n, 3)
+        out["note"] = ("LDS: 16 B per lane per access, conflict-free, 2 workgroups per CU; copy: 16 B per lane, "
+                       "bytes read + written; barrier: two-level device barrier over one workgroup per CU; "
+                       "flags: raise own flag, wait for 8 neighbours, one workgroup per CU")
+    except Exception as e:
+        out["error"] = f"{type(e).__name__}: {e}"
+    return out
+
+
+def _rooflines(gc, dtype, desc, T, updates, dtb_ms, den):
+    b = 8 if dtype == "f64" else 4
+    peak = PEAK_FP64_VECTOR_TFLOPS if dtype == "f64" else PEAK_FP32_VECTOR_TFLOPS
+    tflops = FLOPS_PER_UPDATE * gc / 1e3
+    r = {"valu_TFLOPs": round(tflops, 3), "valu_peak_TFLOPs": peak, "frac_of_valu_peak": round(tflops / peak, 4),
+         "frac_of_untiled_hbm_roofline": round(gc / (PEAK_HBM_GBS / (2 * b)), 3)}
+    if desc is not None and desc.get("path") in (2, 3):
+        lds = _lds_bytes_per_launch(desc, T, b)
+        rate = lds / (dtb_ms / 1e3) / 1e12
+        r["lds_bytes_per_cell_update"] = round(lds / updates, 3)
+        r["lds_TBs"] = round(rate, 3)
+        meas = den.get("lds_read_TBs") and den.get("lds_write_TBs")
+        if meas:
+            r["frac_of_measured_lds_bandwidth"] = round(rate / ((den["lds_read_TBs"] + den["lds_write_TBs"]) / 2), 4)
+        r["frac_of_datasheet_lds_bandwidth"] = round(rate / PEAK_LDS_TBS, 4)
+    return r
+
+
+def _one_config(dtb, inputs, torch, np, stream, name, records, den, reps=5):
     w = inputs.workload(name)
     dt = torch.float64 if w.dtype == "f64" else torch.float32
-    g = torch.from_numpy(w.grid()).to(device="cuda", dtype=dt)
-    T = w.T if T is None else T
+    u0 = torch.from_numpy(w.grid()).to(device="cuda", dtype=dt)
+    g = u0.clone()
     plan = dtb.plan_for(g, w.T)
-    plan.run(g, w.coeffs, min(warm, T))
-    torch.cuda.synchronize()
-    ms = _time_run(plan, g, w.coeffs, T, torch, stream)
+    plan.run(g, w.coeffs, w.T)       # warm-up
+    plan.check()
+    g.copy_(u0)
+    ms = _time_runs(lambda: plan.run(g, w.coeffs, w.T), torch, stream, reps)
+    plan.check()
     d = plan.describe()
     plan.destroy()
-    # The one-step-per-launch kernel on the same grid and step count.
-    sp = dtb.plan_for(g, T, path=dtb.PATH_STEP)
-    sp.run(g, w.coeffs, min(warm, T))
-    torch.cuda.synchronize()
-    sms = _time_run(sp, g, w.coeffs, T, torch, stream)
-    sp.destroy()
-    del g
+    launches, graph_ms = _step_baseline(dtb, torch, stream, g, u0, w.coeffs, w.T, reps)
+    del g, u0
     torch.cuda.empty_cache()
-    gc = w.rows * w.cols * T / (ms / 1e3) / 1e9
-    sgc = w.rows * w.cols * T / (sms / 1e3) / 1e9
+    updates = w.cell_updates
+    st = _stats(ms, updates)
     b = 8 if w.dtype == "f64" else 4
-    return {"workload": name, "dtype": w.dtype, "T_timed": T, "ms": round(ms, 3), "GCells_per_s": round(gc, 2),
-            "step_kernel_GCells_per_s": round(sgc, 2), "dtb_speedup": round(gc / sgc, 3),
-            "frac_of_untiled_hbm_roofline": round(gc / (PEAK_HBM_GBS / (2 * b)), 3), "plan": d}
+    if graph_ms:
+        base = _stats(graph_ms, updates)
+        base["variant"] = "HIP graph of the T launches"
+        if launches < base["median_ms"]:
+            base = _stats([launches], updates)
+            base["variant"] = "T stream launches"
+    else:
+        base = _stats([launches], updates)
+        base["variant"] = "T stream launches"
+    base["launches"] = w.T
+    base["achieved_GBs_algorithmic"] = round(base["GCells_per_s"] * 2 * b, 1)
+    copy_key = "copy_64MiB_GBs" if 2 * (w.rows + 2) * (w.cols + 2) * b <= 256 << 20 else "copy_4GiB_GBs"
+    if den.get(copy_key):
+        base["frac_of_measured_copy_bandwidth"] = round(base["achieved_GBs_algorithmic"] / den[copy_key], 3)
+        base["copy_reference"] = copy_key
+    return {"workload": name, "dtype": w.dtype, "T": w.T, "cell_updates": updates, "plan": d, "dtb": st,
+            "step_kernel": base, "dtb_speedup": round(base["median_ms"] / st["median_ms"], 3),
+            "roofline": _rooflines(st["GCells_per_s"], w.dtype, d, w.T, updates, st["median_ms"], den),
+            "error_vs_oracle": _error_for(records, name, w.dtype)}
 
 
-def _batched(dtb, inputs, torch, np, stream):
+def _batched(dtb, inputs, torch, np, stream, records, reps=5):
     probs = inputs.batched_set(5)
     grids = []
     for p in probs:
@@ -156,36 +260,71 @@ def _batched(dtb, inputs, torch, np, stream):
     updates = sum(p.cell_updates for p in probs)
     dtb.run_batched(grids)          # plans, allocates, builds the graph
     dtb.batch_check()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    dtb.run_batched(grids)          # graph replay
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms = _time_runs(lambda: dtb.run_batched(grids), torch, stream, reps)   # graph replays
     dtb.batch_check()
-    ms = e0.elapsed_time(e1)
     # The same grids one at a time through dtb_run (cached plans, built in a first pass).
     for g, c, T in grids:
         dtb.run(g, c, 1)
     torch.cuda.synchronize()
-    e0.record(stream)
-    for g, c, T in grids:
-        dtb.run(g, c, T)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms1 = e0.elapsed_time(e1)
-    return {"workload": "j2d5pt_batch64_seed5", "grids": len(probs), "cell_updates": updates,
-            "ms": round(ms, 3), "GCells_per_s": round(updates / (ms / 1e3) / 1e9, 2),
-            "one_at_a_time_ms": round(ms1, 3), "one_at_a_time_GCells_per_s": round(updates / (ms1 / 1e3) / 1e9, 2),
-            "batched_speedup": round(ms1 / ms, 3)}
+
+    def one_at_a_time():
+        for g, c, T in grids:
+            dtb.run(g, c, T)
+    ms1 = _time_runs(one_at_a_time, torch, stream, reps)
+    st, st1 = _stats(ms, updates), _stats(ms1, updates)
+    return {"workload": "j2d5pt_batch64_seed5", "grids": len(probs), "cell_updates": updates, "dtb_batched": st,
+            "one_at_a_time": st1, "batched_speedup": round(st1["median_ms"] / st["median_ms"], 3),
+            "error_vs_oracle": _error_for(records, "j2d5pt_batch64_seed5", "f64+f32")}
 
 
-def _extras(dtb, inputs, torch, np, stream):
+def _designs(dtb, inputs, torch, np, stream, name, reps=5):
+    """The same workload under the synchronisation designs the paper weighs: neighbour epoch flags (the
+    default), a device-wide barrier at every exchange (Section 3.2 as printed; resident grids only), and
+    overlapped per-workgroup blocking with no synchronisation between workgroups (Section 2)."""
+    w = inputs.workload(name)
+    dt = torch.float64 if w.dtype == "f64" else torch.float32
+    u0 = torch.from_numpy(w.grid()).to(device="cuda", dtype=dt)
+    g = u0.clone()
+    out = {"workload": name}
+    variants = [("neighbour_flags", {}), ("grid_barrier", dict(path=dtb.PATH_RESIDENT, sync=dtb.SYNC_GRID_BARRIER)),
+                ("overlapped", dict(path=dtb.PATH_OVERLAPPED))]
+    for label, opts in variants:
+        try:
+            plan = dtb.plan_for(g, w.T, **opts)
+        except dtb.DtbError as e:
+            out[label] = {"error": str(e)}
+            continue
+        g.copy_(u0)
+        plan.run(g, w.coeffs, w.T)
+        plan.check()
+        ms = _time_runs(lambda: plan.run(g, w.coeffs, w.T), torch, stream, reps)
+        plan.check()
+        out[label] = {"plan": plan.describe(), **_stats(ms, w.cell_updates)}
+        plan.destroy()
+    base = out.get("neighbour_flags", {}).get("median_ms")
+    for label, _ in variants[1:]:
+        if base and "median_ms" in out.get(label, {}):
+            out[label]["time_vs_neighbour_flags"] = round(out[label]["median_ms"] / base, 3)
+    del g, u0
+    torch.cuda.empty_cache()
+    return out
+
+
+SECONDARY = [("cfg1_256_f64", "j2d5pt_256x256_f64_T16", 100),
+             ("cfg2_2048_f64_resident", "j2d5pt_2048x2048_f64_T10000", 5),
+             ("cfg3_8192_f64_sweep", "j2d5pt_8192x8192_f64_T1000", 5),
+             ("cfg4a_3072_f32_resident", "j2d5pt_3072x3072_f32_T2000", 5),
+             ("cfg4a_3072_f64_sweep", "j2d5pt_3072x3072_f64_T2000", 5),
+             ("cfg4b_16384_f32_sweep", "j2d5pt_16384x16384_f32_T2000", 5)]
+
+
+def _extras(dtb, inputs, torch, np, stream, records, den, skip):
     out = {}
-    jobs = [("fp32_resident_3072", lambda: _one_config(dtb, inputs, torch, np, stream, "j2d5pt_3072x3072_f32_T2000")),
-            ("fp64_sweep_8192", lambda: _one_config(dtb, inputs, torch, np, stream, "j2d5pt_8192x8192_f64_T1000")),
-            ("fp32_sweep_16384", lambda: _one_config(dtb, inputs, torch, np, stream, "j2d5pt_16384x16384_f32_T2000",
-                                                     T=400)),
-            ("batched_64", lambda: _batched(dtb, inputs, torch, np, stream))]
+    jobs = [(key, (lambda n=name, r=reps: _one_config(dtb, inputs, torch, np, stream, n, records, den, r)))
+            for key, name, reps in SECONDARY if name != skip]
+    jobs.append(("cfg5_batch64", lambda: _batched(dtb, inputs, torch, np, stream, records)))
+    jobs.append(("designs_2048_f64", lambda: _designs(dtb, inputs, torch, np, stream, "j2d5pt_2048x2048_f64_T10000")))
+    jobs.append(("designs_8192_f64", lambda: _designs(dtb, inputs, torch, np, stream, "j2d5pt_8192x8192_f64_T1000")))
     for key, fn in jobs:
         print(f"[bench] {key}", file=sys.stderr, flush=True)
         try:
@@ -195,16 +334,47 @@ def _extras(dtb, inputs, torch, np, stream):
     return out
 
 
+def _cpu_baseline(w, budget_s: float):
+    """Time the CPU oracle on a bounded number of steps of the same grid."""
+    import oracle  # test infrastructure, used only for this leg
+    u = w.grid()
+    nt = oracle.default_threads()
+    steps, t0 = 0, time.perf_counter()
+    chunk = max(1, min(50, int(2e9 // (w.rows * w.cols))))
+    while time.perf_counter() - t0 < budget_s and steps < w.T:
+        u = oracle.j2d5pt_f64(u, w.coeffs, chunk, nthreads=nt)
+        steps += chunk
+    dt = time.perf_counter() - t0
+    u1 = w.grid()
+    s1, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < budget_s / 4 and s1 < w.T:
+        u1 = oracle.j2d5pt_f64(u1, w.coeffs, 1, nthreads=1)
+        s1 += 1
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": round(w.rows * w.cols * steps / dt / 1e9, 4), "unit": "GCells/s", "cores": nt,
+            "kind": "oracle",
+            "sample": f"{w.rows}x{w.cols} FP64, {steps} of the {w.T} time steps ({dt:.1f} s, {nt} threads)",
+            "one_thread_value": round(w.rows * w.cols * s1 / dt1 / 1e9, 4),
+            "one_thread_sample": f"{s1} steps ({dt1:.1f} s)", "host_cpu": model, "host_cpus": os.cpu_count()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="j2d5pt_2048x2048_f64_T10000")
+    ap.add_argument("--workload", default=HEADLINE)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-step-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary configurations")
+    ap.add_argument("--no-probes", action="store_true", help="skip the micro-benchmarks of the denominators")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB three times with an "
                          "elementwise kernel (a plain copy of known size, to scale hardware byte counters)")
@@ -214,7 +384,7 @@ def main() -> int:
                          "and report the time per step spent in steps and in each exchange phase")
     args = ap.parse_args()
     if args.source_hash:
-        print(_kernel_source_hash())
+        print(_source_hash())
         return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -255,79 +425,48 @@ def main() -> int:
     kern_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)]
     avg_ms = float(np.mean(kern_ms))
     ms_per_step = wall * 1e3 / args.steps
-    updates = w.rows * w.cols * w.T
+    updates = w.cell_updates
     value = updates * args.steps / wall / 1e9
+    print(f"[bench] timed {args.steps} runs: {value:.1f} GCells/s", file=sys.stderr, flush=True)
 
-    # The untiled baseline on the same grid: T launches of the one-step kernel.
     base = None
     if not args.no_step_baseline:
-        sp = dtb.plan_for(g, w.T, path=dtb.PATH_STEP)
-        g.copy_(u0)
-        sp.run(g, w.coeffs, 200)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        sp.run(g, w.coeffs, w.T)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        bms_launch = e0.elapsed_time(e1)
-        # The same T launches captured once in a HIP graph and replayed (no
-        # per-launch host overhead); the faster of the two is the baseline.
-        bms_graph = None
-        try:
-            side = torch.cuda.Stream()
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.stream(side):
-                with torch.cuda.graph(graph, stream=side):
-                    sp.run(g, w.coeffs, w.T, stream=side)
-            graph.replay()
-            torch.cuda.synchronize()
-            e0.record(stream)
-            graph.replay()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            bms_graph = e0.elapsed_time(e1)
-            del graph
-        except Exception as e:  # the launch-by-launch figure stands on its own
-            print(f"[bench] step-kernel graph skipped: {type(e).__name__}: {e}", file=sys.stderr, flush=True)
-        bms = min(bms_launch, bms_graph) if bms_graph is not None else bms_launch
+        launches, graph_ms = _step_baseline(dtb, torch, stream, g, u0, w.coeffs, w.T, 3)
+        bms = min([launches] + (graph_ms or []))
         bval = updates / (bms / 1e3) / 1e9
-        bytes_per_update = 2 * (8 if w.dtype == "f64" else 4)
+        b = 8 if w.dtype == "f64" else 4
         base = {"value": round(bval, 3), "unit": "GCells/s", "ms_per_run": round(bms, 3),
-                "ms_per_run_launches": round(bms_launch, 3),
-                "ms_per_run_graph": None if bms_graph is None else round(bms_graph, 3),
+                "ms_per_run_launches": round(launches, 3),
+                "ms_per_run_graph": None if not graph_ms else [round(x, 3) for x in graph_ms],
                 "launches": w.T, "dtb_speedup": round(value / bval, 3),
-                "hbm_roofline_GCells": PEAK_HBM_GBS / bytes_per_update,
-                "achieved_GBs_algorithmic": round(bval * bytes_per_update, 1)}
-        sp.destroy()
+                "hbm_roofline_GCells": PEAK_HBM_GBS / (2 * b),
+                "achieved_GBs_algorithmic": round(bval * 2 * b, 1)}
+        print(f"[bench] one-step kernel: {bval:.1f} GCells/s", file=sys.stderr, flush=True)
 
     if args.copy_probe_mb > 0:
         n = args.copy_probe_mb * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
+        bb = torch.empty_like(a)
         for _ in range(3):
-            torch.mul(a, 1.0, out=b)  # an elementwise kernel: reads and writes the buffer once each
+            torch.mul(a, 1.0, out=bb)  # an elementwise kernel: reads and writes the buffer once each
         torch.cuda.synchronize()
         print(f"[bench] copy probe: 3 copies of {args.copy_probe_mb} MiB", file=sys.stderr, flush=True)
-        del a, b
+        del a, bb
 
-    b = 8 if w.dtype == "f64" else 4
-    # Context figures: the untiled kernel's HBM roofline (one read and one write
-    # per cell-step) and the LDS roofline at one LDS read and write per
-    # cell-step (128 B per clock per CU); the DTB kernel keeps its tile in
-    # registers and is bound by neither.
-    hbm_roof = PEAK_HBM_GBS / (2 * b)
-    lds_roof = 256 * 2.4e9 * 128 / (2 * b) / 1e9
-    context = {"untiled_hbm_roofline_GCells": hbm_roof, "frac_of_untiled_hbm_roofline": round(value / hbm_roof, 3),
-               "lds_roofline_GCells": round(lds_roof, 1), "frac_of_lds_roofline": round(value / lds_roof, 3)}
+    den = {} if args.no_probes else _denominators(dtb)
+    records = _accuracy_records()
 
     peak = PEAK_FP64_VECTOR_TFLOPS if w.dtype == "f64" else PEAK_FP32_VECTOR_TFLOPS
     achieved = FLOPS_PER_UPDATE * updates / (avg_ms / 1e3) / 1e12
+    kname = {2: "k_dtb", 3: "k_dtb_sweep"}.get(desc["path"], "k_step")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": _recorded_traffic(w.name),
-            "kernel": "k_dtb", "avg_launch_ms": round(avg_ms, 4),
+            "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
             "launch_ms_min_median_max": [round(min(kern_ms), 4), round(float(np.median(kern_ms)), 4),
-                                         round(max(kern_ms), 4)]}
+                                         round(max(kern_ms), 4)],
+            "algorithmic_flops_per_launch": FLOPS_PER_UPDATE * updates}
+    context = _rooflines(value, w.dtype, desc, w.T, updates, avg_ms, den)
+    context["error_vs_oracle"] = _error_for(records, w.name, w.dtype)
 
     phases = None
     if args.phase_clocks:
@@ -342,10 +481,13 @@ def main() -> int:
         phases = {k: round(float(np.mean([c[k] for c in clocks])) / w.T, 4) for k in keys}
         phases["unit"] = "us per time step, mean over workgroups"
         phases["exchanges"] = int(max(c["exchanges"] for c in clocks))
+    plan.destroy()
+    del g, u0
+    torch.cuda.empty_cache()
 
     extras = {}
     if not args.no_extras:
-        extras = _extras(dtb, inputs, torch, np, stream)
+        extras = _extras(dtb, inputs, torch, np, stream, records, den, w.name)
 
     cpu = None if args.no_cpu else _cpu_baseline(w, args.cpu_budget)
 
@@ -366,13 +508,13 @@ def main() -> int:
                    "weights": w.weights, "seed": w.seed, "plan": desc},
         "roofline": roof,
         "context": context,
+        "denominators": den,
         "phase_clocks": phases,
         "baseline_1step": base,
         "cpu_baseline": cpu,
         "other_configs": extras,
     }
     print(json.dumps(out))
-    plan.destroy()
     return 0
 
 

@@ -60,7 +60,11 @@ typedef enum {
     DTB_PATH_AUTO = 0,     /* resident DTB when the grid fits on chip, else the tile-serial sweep */
     DTB_PATH_STEP = 1,     /* the untiled baseline: one kernel launch per time step, HBM to HBM */
     DTB_PATH_RESIDENT = 2, /* deep temporal blocking, whole grid held on chip for all T steps */
-    DTB_PATH_SWEEP = 3     /* deep temporal blocking, big tiles processed one after another (tile-serial) */
+    DTB_PATH_SWEEP = 3,    /* deep temporal blocking, big tiles processed one after another (tile-serial) */
+    DTB_PATH_OVERLAPPED = 4 /* overlapped per-workgroup blocking (Section 2's "overlapped tiling within
+                               thread blocks"): one launch per depth_D steps, each workgroup loads its tile
+                               with a depth_D-deep ring from HBM, advances it depth_D steps with no
+                               synchronisation between workgroups and stores its owned cells; for comparison */
 } dtb_path;
 
 /* A grid in device memory (see the storage description above). */
@@ -75,7 +79,8 @@ typedef struct {
 typedef struct {
     int32_t path;        /* dtb_path */
     int32_t ghost_k;     /* steps between inter-workgroup halo exchanges (ghost ring depth); 0 = auto */
-    int32_t depth_D;     /* sweep: steps per round (temporal depth of a big tile); 0 = auto */
+    int32_t depth_D;     /* sweep: steps per round (temporal depth of a big tile); overlapped path: steps
+                            per launch (ring depth of a tile); 0 = auto */
     int32_t rows_per_lane; /* register tile height per lane; 0 = auto.  Instantiated: FP64 8, 16, 24
                               (2 columns per lane) and 12 (4 columns per lane); FP32 8, 16, 24, 28
                               (4 columns per lane).  Tiles are 8 waves x rows_per_lane rows high. */
@@ -88,6 +93,9 @@ typedef struct {
     int32_t waves;       /* waves per workgroup of the resident path: 8, or 4 (FP64, 24 rows per lane:
                             half-height tiles, two workgroups per compute unit so that one's exchange
                             overlaps the other's steps); 0 = choose */
+    int32_t sync;        /* resident path, what a workgroup waits for at an exchange: 0 = the workgroups
+                            whose cells it reads (neighbour epoch flags); 1 = every workgroup, at a
+                            device-wide barrier (the grid-level barrier of Section 3.2; for comparison) */
 } dtb_plan_opts;
 
 /* Debug bits for dtb_plan_opts.debug_flags. */
@@ -117,6 +125,10 @@ typedef struct {
  * tile decomposition, the exchange depth and the workgroup count, checks that
  * every workgroup can be resident at once, and allocates the plan's device
  * workspace (exchange buffers, epoch flags, error word, descriptor tables).
+ * (The paper: the whole-GPU tiling of the Abstract and Section 1 -- tiles
+ * sized to the on-chip memory of all compute units; several steps per tile
+ * between exchanges, Section 3.2; tiles processed one after another when the
+ * grid is larger than the chip, Section 3.3 and Figure 1.)
  * T_hint is the expected step count (0 = unknown).  opts may be NULL.
  * On success *out receives the plan; release it with dtb_plan_destroy.
  * Allocates; not for use under stream capture.
@@ -125,29 +137,40 @@ dtb_status dtb_plan(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, 
                     int64_t T_hint, const dtb_plan_opts* opts);
 
 /*
- * Advance grid->data by T steps in place with an explicit plan.  The grid's
+ * Advance grid->data by T steps in place with an explicit plan (Listing 1's
+ * update repeated T times, Section 3.1 and Figure 1).  The grid's
  * rows, cols, pitch and dtype must match the plan.  T == 0 returns DTB_OK
- * without launching.  One call in flight per plan; calls on other plans may
- * overlap.  Does not allocate.
+ * without launching.  The plan's workspace serves one run at a time: a call
+ * on another stream than the plan's previous run waits for that run first
+ * (outside stream capture; inside it, runs are ordered by the capturing
+ * stream).  Calls on other plans may overlap.  Does not allocate.
  */
 dtb_status dtb_run_plan(dtb_plan_t plan, const dtb_grid* grid, const double coeffs[5], int64_t T,
                         void* stream);
 
 /*
- * Advance grid->data by T steps in place, using a plan cached by
- * (rows, cols, pitch, dtype, device), created on first use with default
- * options.  Creating the plan allocates; later calls do not.
+ * Advance grid->data by T steps in place (Listing 1's update repeated T
+ * times, Section 3.1 and Figure 1), using a plan cached by (rows, cols,
+ * pitch, dtype, device), created on first use with default options.
+ * Creating the plan allocates; later calls do not.  Calls on the same cached
+ * plan are ordered: a call on another stream than the previous one waits for
+ * the previous run first (outside stream capture).
  */
 dtb_status dtb_run(const dtb_grid* grid, const double coeffs[5], int64_t T, dtb_dtype dtype,
                    void* stream);
 
 /*
  * Run `count` independent problems (uneven shapes, step counts and
- * precisions) in one persistent launch.  The first call for a given set of
+ * precisions) in one persistent launch -- each problem the operation of
+ * dtb_run (Listing 1, Section 3.1).  The first call for a given set of
  * shapes/precisions/step counts plans each problem, packs their workgroups
  * onto the compute units and captures the launch in a HIP graph; later calls
  * with the same signature update the grid pointers and coefficients and
- * replay the graph.  Each grid is updated in place as dtb_run would.
+ * replay the graph.  Each grid is updated in place as dtb_run would.  The
+ * planner picks, per problem, the register-tile shape (two per precision),
+ * the exchange depth and, for grids larger than the chip, the round depth.
+ * Calls with the same signature share one descriptor table: a call on
+ * another stream than the previous one waits for it first.
  */
 dtb_status dtb_run_batched(const dtb_problem* problems, int32_t count, void* stream);
 
@@ -179,7 +202,7 @@ dtb_status dtb_plan_timing(dtb_plan_t plan, uint64_t* out, int32_t n, void* stre
 /*
  * Describe a plan: fills up to `n` int64 values in this order: path,
  * workgroups, ghost_k, depth_D, ext_rows, ext_cols, tiles_rows, tiles_cols,
- * rows_per_lane, cols_per_lane, big_tiles, exact, waves.  Returns DTB_OK.
+ * rows_per_lane, cols_per_lane, big_tiles, exact, waves, sync.  Returns DTB_OK.
  */
 dtb_status dtb_plan_describe(dtb_plan_t plan, int64_t* values, int32_t n);
 

@@ -1,11 +1,14 @@
 /*
- * dtb_testing.h -- host-only hooks into libdtb's planner, for tests that run
- * without a GPU.  Not needed to use the library.
+ * dtb_testing.h -- hooks into libdtb for tests and measurements: the planner
+ * without a GPU, and micro-benchmarks of the part the kernels run on.  Not
+ * needed to use the library.
  */
 #ifndef LIBDTB_DTB_TESTING_H
 #define LIBDTB_DTB_TESTING_H
 
 #include <stdint.h>
+
+#include "dtb.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -48,22 +51,45 @@ int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32
 int32_t dtb_test_sweep(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_t cols_per_lane, int32_t waves,
                        int32_t k, int32_t D, int32_t max_wg, int32_t n_xcd, int32_t* out, int32_t max_records);
 
-#define DTB_TEST_BATCH_STRIDE 10
+#define DTB_TEST_BATCH_STRIDE 13
 
 /*
  * Run the batch planner for `count` problems (rows[i] x cols[i], dtype[i],
- * T[i]) on n_slots workgroup slots with register tiles of r64 / r32 rows per
- * lane.  No HIP call is made.  Returns the number of jobs (== count), or -1.
+ * T[i]) on n_slots workgroup slots.  r64 = r32 = 0: with the register-tile
+ * instances the batched kernel carries; otherwise with one instance per
+ * precision, FP64 2 x r64 and FP32 4 x r32 cells per lane.  No HIP call is
+ * made.  Returns the number of jobs (== count), or -1.
  * `jobs` (count * DTB_TEST_BATCH_STRIDE int32, may be NULL) receives, in
  * global job order: problem, workgroups, sweep (0/1), ntiles, D, nrounds,
- * flag_base, table_off, start (model us, rounded), duration (model us).
+ * flag_base, table_off, start (model us, rounded), duration (model us),
+ * exchange depth k, rows per lane, columns per lane.
  * `slot_lists` (may be NULL; n_slots + 1 offsets followed by the
  * (job, member) pairs, 2 int32 each; size n_slots + 1 + 2 * total members)
- * receives every slot's work list.
+ * receives every slot's work list.  `info` (may be NULL, 2 int64) receives the
+ * modelled makespan (us) and the poll limit of the batch's bounded waits.
  */
 int32_t dtb_test_batch(int32_t count, const int64_t* rows, const int64_t* cols, const int32_t* dtype,
                        const int64_t* T, int32_t r64, int32_t r32, int32_t n_slots, int32_t* jobs,
-                       int32_t* slot_lists, int32_t slot_lists_len);
+                       int32_t* slot_lists, int32_t slot_lists_len, int64_t* info);
+
+/* Micro-benchmark kinds for dtb_probe. */
+#define DTB_PROBE_LDS_READ 0  /* LDS reads, 16 bytes per lane, conflict-free; nwg workgroups (0: 2 per CU) */
+#define DTB_PROBE_LDS_WRITE 1 /* LDS writes, likewise */
+#define DTB_PROBE_COPY 2      /* device-to-device copy of `size` bytes, `iters` times, 16 bytes per lane */
+#define DTB_PROBE_BARRIER 3   /* `iters` device-wide barriers among nwg persistent workgroups (0: one per CU) */
+#define DTB_PROBE_FLAGS 4     /* `iters` neighbour exchange points (flag raised, 8 neighbours awaited), no data */
+
+/*
+ * Run one micro-benchmark on the current device, enqueued on `stream` (a
+ * hipStream_t as void*, NULL = default stream) and timed there with HIP events;
+ * waits for it.  out[0] receives the elapsed milliseconds of the timed part and
+ * out[1] the work it did: bytes moved (LDS, copy: read + written) or the
+ * number of barriers / exchange points.  Allocates and frees its own buffers
+ * (not for use under stream capture).  DTB_ERR_NOT_CORESIDENT if a persistent
+ * probe asks for more workgroups than compute units; DTB_ERR_TIMEOUT if a
+ * bounded wait expired.
+ */
+dtb_status dtb_probe(int32_t kind, int64_t size, int32_t iters, int32_t nwg, void* stream, double* out);
 
 #ifdef __cplusplus
 }

@@ -32,9 +32,22 @@ _HIP = ["-x", "hip", f"--offload-arch={ARCH}"]
 SOURCES = [(f"dtb_inst_{n}.hip", _HIP) for n in ("f32_r28", "f32_r24", "batch", "f64_r24", "f64c4_r12", "f64w4_r24", "f32_r16",
                                                  "f64_r16", "f32_r8", "f64_r8")] + [
     ("dtb_kernels.hip", _HIP),
+    ("dtb_probe.hip", _HIP),
     ("dtb_plan.cpp", []),
     ("dtb_api.cpp", ["-D__HIP_PLATFORM_AMD__"]),
 ]
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the device sources (csrc/*.h, csrc/*.hip): measurements recorded for one
+    version of the kernels (HBM traffic, accuracy) are reported only while this still matches."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def _up_to_date(src: str, obj: str) -> bool:

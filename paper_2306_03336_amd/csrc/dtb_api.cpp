@@ -24,6 +24,7 @@ using namespace dtb;
 namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // bounded wait: a few seconds of polling
+constexpr size_t kBarrierWords = 17 * (size_t)kFlagStride;  // device-wide barrier counters, one slot each
 constexpr int kNumXcd = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
 // Instantiated rows per lane: FP64 8, 16, 24 (2 columns per lane) and 12 (4 columns); FP32 8, 16, 24, 28.
 constexpr int kDtbRowsPerLane[] = {8, 12, 16, 24, 28};
@@ -64,15 +65,24 @@ struct dtb_plan_s {
     void* xbuf[2] = {nullptr, nullptr};
     // tile-serial sweep (uses ws as its second buffer)
     SweepPlan sweep;
+    // overlapped per-workgroup blocking (layout with k = D, ws as its second buffer)
+    int ovl_D = 0;
+    bool grid_sync = false;  // resident path: device-wide barrier at every exchange
     uint32_t* d_bar = nullptr;
     int nwg_launch = 0;
     int debug = 0;
     uint64_t* d_timing = nullptr;  // DTB_DEBUG_TIMING
+    // The workspace serves one run at a time: the last run's stream and an
+    // event recorded after it, which a run on another stream waits for.
+    hipEvent_t done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_run = false;
 
     uint32_t spin_limit() const { return (debug & DTB_DEBUG_TINY_SPIN) ? 4u : kSpinLimit; }
 
     ~dtb_plan_s()
     {
+        if (done) (void)hipEventDestroy(done);
         if (ws) (void)hipFree(ws);
         if (d_bar) (void)hipFree(d_bar);
         if (d_timing) (void)hipFree(d_timing);
@@ -100,13 +110,35 @@ dtb_status check_shape(int64_t rows, int64_t cols, int64_t pitch, int dtype)
 dtb_status check_opts(const dtb_plan_opts* o)
 {
     if (!o) return DTB_OK;
-    if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_SWEEP) return DTB_ERR_INVALID_ARG;
+    if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_OVERLAPPED) return DTB_ERR_INVALID_ARG;
+    if (o->sync != 0 && o->sync != 1) return DTB_ERR_INVALID_ARG;
     if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0) return DTB_ERR_INVALID_ARG;
     if (o->waves != 0 && o->waves != 4 && o->waves != 8) return DTB_ERR_INVALID_ARG;
     if (o->exact != 0 && o->exact != 1) return DTB_ERR_INVALID_ARG;
     if ((o->debug_flags & ~(DTB_DEBUG_TINY_SPIN | DTB_DEBUG_POISON | DTB_DEBUG_TIMING | DTB_DEBUG_DIRECT_XCHG)) != 0 ||
         (o->tune != 0 && o->tune != 1))
         return DTB_ERR_INVALID_ARG;
+    return DTB_OK;
+}
+
+// A requested tile instance must exist: FP64 8, 12, 16, 24 rows per lane and,
+// with 4 waves per workgroup, 24 rows on the resident path only; FP32 8, 16,
+// 24, 28 rows with 8 waves.  Checked before any HIP call.
+dtb_status check_instance(const dtb_plan_opts& o, int dtype)
+{
+    if (o.path == DTB_PATH_STEP) return DTB_OK;
+    if (o.waves == 4 && (dtype != DTB_F64 || o.path == DTB_PATH_SWEEP || o.path == DTB_PATH_OVERLAPPED ||
+                         (o.rows_per_lane != 0 && o.rows_per_lane != 24)))
+        return DTB_ERR_UNSUPPORTED;
+    // The device-wide barrier variant exists for the resident path only.
+    if (o.sync == 1 && (o.path == DTB_PATH_SWEEP || o.path == DTB_PATH_OVERLAPPED || o.tune)) return DTB_ERR_UNSUPPORTED;
+    if (o.rows_per_lane > 0) {
+        int C = 0, waves = 0;
+        const void* f = o.path == DTB_PATH_SWEEP ? dtb_sweep_kernel(dtype, o.rows_per_lane, true, false, false, &C, &waves)
+                      : o.path == DTB_PATH_OVERLAPPED ? dtb_ovl_kernel(dtype, o.rows_per_lane, true, false, false, &C, &waves)
+                      : dtb_kernel(dtype, o.rows_per_lane, true, false, false, &C, &waves, o.waves);
+        if (!f) return DTB_ERR_UNSUPPORTED;
+    }
     return DTB_OK;
 }
 
@@ -151,7 +183,10 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
             const void* f0 = dtb_kernel(dtype, R, fma, false, false, &C, &waves, want_waves);
             if (!f0) continue;
             Layout L;
-            if (!build_layout(rows, cols, interior(rows, cols), interior(rows, cols), R, C, waves, k, kNumXcd, 0, 0, &L))
+            // No more tiles than can be co-resident (at most two workgroups per compute unit): larger
+            // layouts are not even built (at 16384^2 they run to 10^5 tiles).
+            if (!build_layout(rows, cols, interior(rows, cols), interior(rows, cols), R, C, waves, k, kNumXcd, 0, 0, &L,
+                              true, 2 * n_cu))
                 continue;
             const bool cm = L.cols.narrow, rc = L.rows.narrow;
             const void* f = dtb_kernel(dtype, R, fma, cm, rc, &C, &waves, want_waves);
@@ -195,6 +230,60 @@ double sweep_step_us(const SweepPlan& sp, int dtype)
         total += sp.D * t_step + ((double)sp.D / sp.k) * t_exch + t_bar + io;
     }
     return total / sp.D;
+}
+
+// Overlapped per-workgroup blocking: every workgroup runs D steps on its own
+// tile and moves the tile through HBM once per D steps.  Model per time step:
+// the workgroups run in ceil(nwg / slots) waves; each workgroup spends D
+// register-tile steps plus its tile's load and store at its share of HBM
+// bandwidth (4 TB/s over the slots) -- a load cannot overlap the tile's own
+// steps.
+double overlapped_step_us(const Layout& L, int slots, int elem_bytes)
+{
+    const double waves = std::ceil((double)L.nwg / std::max(slots, 1));
+    const double t_step = tile_step_time_us(L.ER, L.EC, elem_bytes);
+    const double io = (double)L.ER * L.EC * elem_bytes * 2.0 / (4.0e6 / std::max(slots, 1)) + 2.0;
+    return waves * (L.k * t_step + io) / L.k;
+}
+
+bool choose_overlapped(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o, int n_cu, bool fma,
+                       Layout* best_layout, const void** best_func, bool* colmask, bool* rowcheck)
+{
+    double best = 1e300;
+    bool found = false;
+    std::vector<int> Ds;
+    if (o.depth_D > 0) Ds.push_back(o.depth_D);
+    else
+        for (int D = 2; D <= 32; ++D) Ds.push_back(D);
+    for (int R : kDtbRowsPerLane) {
+        if (o.rows_per_lane > 0 && o.rows_per_lane != R) continue;
+        int C = 0, waves = 0;
+        if (!dtb_ovl_kernel(dtype, R, fma, false, false, &C, &waves)) continue;
+        for (int D : Ds) {
+            Layout L;
+            if (!build_layout(rows, cols, interior(rows, cols), interior(rows, cols), R, C, waves, D, kNumXcd, 0, 0, &L,
+                              false))
+                continue;
+            const bool cm = L.cols.narrow, rc = L.rows.narrow;
+            const void* f = dtb_ovl_kernel(dtype, R, fma, cm, rc, &C, &waves);
+            if (!f || spills(f)) continue;
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) != hipSuccess || occ < 1)
+                continue;
+            int slots = occ * n_cu;
+            if (o.max_wg > 0) slots = std::min(slots, o.max_wg);
+            const double cost = overlapped_step_us(L, slots, dtype == DTB_F64 ? 8 : 4);
+            if (cost < best) {
+                best = cost;
+                *best_layout = std::move(L);
+                *best_func = f;
+                *colmask = cm;
+                *rowcheck = rc;
+                found = true;
+            }
+        }
+    }
+    return found;
 }
 
 bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o, int n_cu, bool fma, SweepPlan* best,
@@ -315,7 +404,7 @@ std::vector<std::pair<double, TuneChoice>> tune_candidates(int64_t rows, int64_t
             if (o.path == DTB_PATH_AUTO || o.path == DTB_PATH_RESIDENT) {
                 Layout L;
                 if (build_layout(rows, cols, interior(rows, cols), interior(rows, cols), R, C, waves, k, kNumXcd, 0,
-                                 0, &L)) {
+                                 0, &L, true, 2 * n_cu)) {
                     const void* f = dtb_kernel(dtype, R, fma, L.cols.narrow, L.rows.narrow, &C, &waves);
                     int occ = 0;
                     if (f && !spills(f) &&
@@ -449,7 +538,10 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
     if (st != DTB_OK) return st;
     dtb_plan_opts o{};
     if (opts) o = *opts;
-    if (o.tune && o.path != DTB_PATH_STEP) return tune_plan(out, rows, cols, pitch, dtype, T_hint, o);
+    st = check_instance(o, dtype);
+    if (st != DTB_OK) return st;
+    if (o.tune && o.path != DTB_PATH_STEP && o.path != DTB_PATH_OVERLAPPED)
+        return tune_plan(out, rows, cols, pitch, dtype, T_hint, o);
 
     DeviceInfo di;
     if (!device_info(&di)) return DTB_ERR_HIP;
@@ -464,6 +556,17 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
     const size_t bytes = (size_t)(rows + 2) * (size_t)pitch * elem_size(dtype);
 
     int path = o.path;
+    if (path == DTB_PATH_OVERLAPPED) {
+        Layout L;
+        const void* f = nullptr;
+        bool cm = false, rc = false;
+        if (!choose_overlapped(rows, cols, dtype, o, di.n_cu, p->fma, &L, &f, &cm, &rc)) return DTB_ERR_UNSUPPORTED;
+        p->ovl_D = L.k;
+        p->layout = std::move(L);
+        p->kfunc = f;
+        p->colmask = cm;
+        p->rowcheck = rc;
+    }
     if (path == DTB_PATH_AUTO || path == DTB_PATH_RESIDENT) {
         Layout L;
         const void* f = nullptr;
@@ -479,6 +582,10 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
         } else {
             path = DTB_PATH_SWEEP;  // larger than the chip: big tiles one after another
         }
+    }
+    if (o.sync == 1) {
+        if (path != DTB_PATH_RESIDENT) return DTB_ERR_UNSUPPORTED;
+        p->grid_sync = true;
     }
     if (path == DTB_PATH_SWEEP) {
         const void* f = nullptr;
@@ -496,6 +603,12 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
 
     if (path == DTB_PATH_STEP) {
         if (hipMalloc(&p->ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+    } else if (path == DTB_PATH_OVERLAPPED) {
+        const size_t nwg = p->layout.wgs.size();
+        if (hipMalloc(&p->ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_wgs, nwg * sizeof(WgDesc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMemcpy(p->d_wgs, p->layout.wgs.data(), nwg * sizeof(WgDesc), hipMemcpyHostToDevice) != hipSuccess)
+            return DTB_ERR_HIP;
     } else if (path == DTB_PATH_SWEEP) {
         const size_t n = p->sweep.table.size();
         const size_t nwg = (size_t)p->nwg_launch;
@@ -503,14 +616,14 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
         if (hipMalloc(&p->d_wgs, n * sizeof(WgDesc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMalloc(&p->d_flags, nwg * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMalloc(&p->d_err, sizeof(int)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
-        if (hipMalloc(&p->d_bar, 17 * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&p->d_bar, kBarrierWords * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         for (int i = 0; i < 2; ++i)
             if (hipMalloc(&p->xbuf[i], bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMemcpy(p->d_wgs, p->sweep.table.data(), n * sizeof(WgDesc), hipMemcpyHostToDevice) != hipSuccess)
             return DTB_ERR_HIP;
         if (hipMemset(p->d_flags, 0, nwg * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
         if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
-        if (hipMemset(p->d_bar, 0, 17 * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+        if (hipMemset(p->d_bar, 0, kBarrierWords * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
     } else {
         const size_t nwg = p->layout.wgs.size();
         if (hipMalloc(&p->d_wgs, nwg * sizeof(WgDesc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
@@ -522,8 +635,13 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
             return DTB_ERR_HIP;
         if (hipMemset(p->d_flags, 0, nwg * kFlagStride * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
         if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return DTB_ERR_HIP;
+        if (p->grid_sync) {
+            if (hipMalloc(&p->d_bar, kBarrierWords * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+            if (hipMemset(p->d_bar, 0, kBarrierWords * sizeof(uint32_t)) != hipSuccess) return DTB_ERR_HIP;
+        }
     }
-    if ((p->debug & DTB_DEBUG_TIMING) && path != DTB_PATH_STEP) {
+    if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) return DTB_ERR_HIP;
+    if ((p->debug & DTB_DEBUG_TIMING) && path != DTB_PATH_STEP && path != DTB_PATH_OVERLAPPED) {
         const size_t n = (size_t)std::max<int>(p->nwg_launch, p->layout.nwg) * kTimingSlots;
         if (hipMalloc(&p->d_timing, n * sizeof(uint64_t)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
         if (hipMemset(p->d_timing, 0, n * sizeof(uint64_t)) != hipSuccess) return DTB_ERR_HIP;
@@ -553,6 +671,11 @@ dtb_status run_step(dtb_plan_t p, void* data, const double* coeffs, int64_t T, h
 dtb_status poison_xbufs(dtb_plan_t p, hipStream_t st)
 {
     if (!(p->debug & DTB_DEBUG_POISON)) return DTB_OK;
+    // A debug aid for direct launches only: memset nodes recorded into a
+    // captured graph are not replayed reliably.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return DTB_ERR_HIP;
+    if (cs != hipStreamCaptureStatusNone) return DTB_ERR_UNSUPPORTED;
     const size_t bytes = (size_t)(p->rows + 2) * (size_t)p->pitch * elem_size(p->dtype);
     for (void* x : p->xbuf)
         if (x && hipMemsetAsync(x, 0xFF, bytes, st) != hipSuccess) return DTB_ERR_HIP;
@@ -561,7 +684,7 @@ dtb_status poison_xbufs(dtb_plan_t p, hipStream_t st)
 
 dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t T, hipStream_t st)
 {
-    if (poison_xbufs(p, st) != DTB_OK) return DTB_ERR_HIP;
+    if (dtb_status rc = poison_xbufs(p, st); rc != DTB_OK) return rc;
     ProbDesc P{};
     P.grid = data;
     P.xbuf[0] = p->xbuf[0];
@@ -580,6 +703,9 @@ dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t 
     P.debug = p->debug;
     P.timing = p->d_timing;
     P.direct_xchg = (p->debug & DTB_DEBUG_DIRECT_XCHG) ? 1 : 0;
+    P.grid_sync = p->grid_sync ? 1 : 0;
+    P.bar = p->d_bar;
+    if (p->grid_sync && launch_reset_counter(p->d_bar, st) != hipSuccess) return DTB_ERR_HIP;
     for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
     const WgDesc* wgs = p->d_wgs;
     uint32_t* flags = p->d_flags;
@@ -591,9 +717,49 @@ dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t 
     return DTB_OK;
 }
 
+// Overlapped per-workgroup blocking: rounds of D steps, one launch each,
+// between the grid and the workspace (whose halo ring is copied first); after
+// an odd number of rounds the interior is copied back.
+dtb_status run_overlapped_path(dtb_plan_t p, void* data, const double* coeffs, int64_t T, hipStream_t st)
+{
+    const int rows = (int)p->rows, cols = (int)p->cols;
+    const int D = p->ovl_D;
+    if (launch_copy_halo(p->dtype, data, p->ws, p->pitch, rows, cols, st) != hipSuccess) return DTB_ERR_HIP;
+    ProbDesc P{};
+    P.grid = data;
+    P.pitch = p->pitch;
+    P.T = T;
+    P.rows = rows;
+    P.cols = cols;
+    P.k = D;
+    P.nwg = p->layout.nwg;
+    P.dtype = p->dtype;
+    P.fma = p->fma ? 1 : 0;
+    P.narrow_cols = p->colmask ? 1 : 0;
+    P.narrow_rows = p->rowcheck ? 1 : 0;
+    for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
+    const WgDesc* wgs = p->d_wgs;
+    void* bufs[2] = {data, p->ws};
+    const dim3 grid(p->layout.nwg), block(p->layout.waves * kWaveSize);
+    int64_t done = 0, round = 0;
+    while (done < T) {
+        int steps = (int)std::min<int64_t>(D, T - done);
+        void* src = bufs[round & 1];
+        void* dst = bufs[(round + 1) & 1];
+        void* args[] = {&P, (void*)&wgs, &src, &dst, &steps};
+        if (hipLaunchKernel(p->kfunc, grid, block, args, 0, st) != hipSuccess) return DTB_ERR_HIP;
+        done += steps;
+        ++round;
+    }
+    if (round & 1) {
+        if (launch_copy_interior(p->dtype, p->ws, data, p->pitch, rows, cols, st) != hipSuccess) return DTB_ERR_HIP;
+    }
+    return DTB_OK;
+}
+
 dtb_status run_sweep(dtb_plan_t p, void* data, const double* coeffs, int64_t T, hipStream_t st)
 {
-    if (poison_xbufs(p, st) != DTB_OK) return DTB_ERR_HIP;
+    if (dtb_status rc = poison_xbufs(p, st); rc != DTB_OK) return rc;
     const int rows = (int)p->rows, cols = (int)p->cols;
     const SweepPlan& sp = p->sweep;
     // The second buffer needs the grid's halo: the kernel reads it from whichever buffer is current.
@@ -641,6 +807,20 @@ dtb_status run_sweep(dtb_plan_t p, void* data, const double* coeffs, int64_t T, 
     return DTB_OK;
 }
 
+// A run on a stream other than the previous run's waits for the previous run
+// (its workspace -- exchange buffers, flags, sweep buffer, descriptor table --
+// is shared).  Inside a stream capture the wait is left out: an event recorded
+// outside the capture cannot be waited on there, and runs captured on one
+// stream are ordered by that stream.
+dtb_status order_after_last_run(hipEvent_t done, bool has_run, hipStream_t last, hipStream_t st)
+{
+    if (!has_run || last == st) return DTB_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return DTB_ERR_HIP;
+    if (cs != hipStreamCaptureStatusNone) return DTB_OK;
+    return hipStreamWaitEvent(st, done, 0) == hipSuccess ? DTB_OK : DTB_ERR_HIP;
+}
+
 dtb_status run_plan_impl(dtb_plan_t p, const dtb_grid* g, const double* coeffs, int64_t T, void* stream)
 {
     if (!p || !g || !coeffs || !g->data) return DTB_ERR_INVALID_ARG;
@@ -648,10 +828,17 @@ dtb_status run_plan_impl(dtb_plan_t p, const dtb_grid* g, const double* coeffs, 
     if (g->rows != p->rows || g->cols != p->cols || g->pitch != p->pitch) return DTB_ERR_MISMATCH;
     if (T == 0) return DTB_OK;
     hipStream_t st = (hipStream_t)stream;
-    if (p->path == DTB_PATH_STEP) return run_step(p, g->data, coeffs, T, st);
-    if (p->path == DTB_PATH_RESIDENT) return run_resident(p, g->data, coeffs, T, st);
-    if (p->path == DTB_PATH_SWEEP) return run_sweep(p, g->data, coeffs, T, st);
-    return DTB_ERR_UNSUPPORTED;
+    if (dtb_status rc = order_after_last_run(p->done, p->has_run, p->last_stream, st); rc != DTB_OK) return rc;
+    dtb_status rc = DTB_ERR_UNSUPPORTED;
+    if (p->path == DTB_PATH_STEP) rc = run_step(p, g->data, coeffs, T, st);
+    else if (p->path == DTB_PATH_RESIDENT) rc = run_resident(p, g->data, coeffs, T, st);
+    else if (p->path == DTB_PATH_SWEEP) rc = run_sweep(p, g->data, coeffs, T, st);
+    else if (p->path == DTB_PATH_OVERLAPPED) rc = run_overlapped_path(p, g->data, coeffs, T, st);
+    if (rc != DTB_OK) return rc;
+    if (hipEventRecord(p->done, st) != hipSuccess) return DTB_ERR_HIP;
+    p->last_stream = st;
+    p->has_run = true;
+    return DTB_OK;
 }
 
 // ---- dtb_run's plan cache
@@ -671,7 +858,8 @@ std::map<CacheKey, dtb_plan_t> g_cache;
 struct BatchEntry {
     int device = -1;
     BatchPlan plan;
-    int r64 = 0, r32 = 0;
+    TileInst insts[kMaxBatchInsts];
+    int ninst = 0;
     std::vector<ProbDesc> probs;  // templates: everything but grid pointer and coefficients
     ProbDesc* d_probs = nullptr;
     JobDesc* d_jobs = nullptr;
@@ -687,9 +875,14 @@ struct BatchEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool cooperative = false;
+    uint32_t spin = kSpinLimit;       // bounded waits of this batch (see batch_spin_limit)
+    hipEvent_t done = nullptr;        // recorded after every replay
+    hipStream_t last_stream = nullptr;
+    bool has_run = false;
 
     ~BatchEntry()
     {
+        if (done) (void)hipEventDestroy(done);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (int i = 0; i < 2; ++i) {
@@ -712,7 +905,7 @@ dtb_status make_batch(const dtb_problem* problems, int32_t count, int device, Ba
     if (!device_info(&di)) return DTB_ERR_HIP;
     std::unique_ptr<BatchEntry> b(new BatchEntry());
     b->device = device;
-    const void* kfn = batched_kernel(&b->r64, &b->r32);
+    const void* kfn = batched_kernel(b->insts, &b->ninst);
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, 8 * kWaveSize, 0) != hipSuccess) return DTB_ERR_HIP;
     const int nslots = std::min(occ, 1) * di.n_cu;
@@ -725,7 +918,8 @@ dtb_status make_batch(const dtb_problem* problems, int32_t count, int device, Ba
         specs[i].T = problems[i].T;
         specs[i].dtype = problems[i].dtype;
     }
-    if (!plan_batch(specs, b->r64, b->r32, 8, nslots, &b->plan)) return DTB_ERR_UNSUPPORTED;
+    if (!plan_batch(specs, std::vector<TileInst>(b->insts, b->insts + b->ninst), 8, nslots, &b->plan))
+        return DTB_ERR_UNSUPPORTED;
     const BatchPlan& bp = b->plan;
 
     // Per problem: two exchange buffers; per sweep job: the second grid buffer.
@@ -762,6 +956,8 @@ dtb_status make_batch(const dtb_problem* problems, int32_t count, int device, Ba
         D.D = J.D;
         D.nrounds = J.nrounds;
         D.sweep = J.sweep ? 1 : 0;
+        D.R = J.R;
+        D.C = J.C;
         D.ws = nullptr;
         if (J.sweep) {
             if (hipMalloc(&D.ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
@@ -795,9 +991,10 @@ dtb_status make_batch(const dtb_problem* problems, int32_t count, int device, Ba
 
     // One kernel node: the persistent batched kernel over every slot.
     if (hipGraphCreate(&b->graph, 0) != hipSuccess) return DTB_ERR_HIP;
-    static uint32_t spin = kSpinLimit;
+    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) return DTB_ERR_HIP;
+    b->spin = batch_spin_limit(bp.makespan, kSpinLimit);
     void* args[] = {(void*)&b->d_probs, (void*)&b->d_jobs, (void*)&b->d_table, (void*)&b->d_wl_off,
-                    (void*)&b->d_wl, (void*)&b->d_flags, (void*)&b->d_err, (void*)&spin};
+                    (void*)&b->d_wl, (void*)&b->d_flags, (void*)&b->d_err, (void*)&b->spin};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(kfn);
     kp.gridDim = dim3(nslots);
@@ -807,10 +1004,16 @@ dtb_status make_batch(const dtb_problem* problems, int32_t count, int device, Ba
     kp.extra = nullptr;
     hipGraphNode_t node = nullptr;
     if (hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) != hipSuccess) return DTB_ERR_HIP;
+    // Every wait in the batched kernel relies on all slots being resident at
+    // once: without the cooperative attribute there is no such guarantee, so
+    // refuse rather than replay an ordinary launch.
     hipKernelNodeAttrValue v{};
     v.cooperative = 1;
-    b->cooperative = hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v) == hipSuccess;
-    (void)hipGetLastError();
+    if (hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v) != hipSuccess) {
+        (void)hipGetLastError();
+        return DTB_ERR_UNSUPPORTED;
+    }
+    b->cooperative = true;
     if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) return DTB_ERR_HIP;
     *out = b.release();
     return DTB_OK;
@@ -838,6 +1041,8 @@ dtb_status run_batched_impl(const dtb_problem* problems, int32_t count, hipStrea
         if (rc != DTB_OK) return rc;
         g_batch_cache[key] = b;
     }
+    // The descriptor table and the flags serve one replay at a time.
+    if (dtb_status rc = order_after_last_run(b->done, b->has_run, b->last_stream, st); rc != DTB_OK) return rc;
     // This call's grid pointers and coefficients into the descriptor table.
     const int s = b->stage;
     b->stage ^= 1;
@@ -852,6 +1057,9 @@ dtb_status run_batched_impl(const dtb_problem* problems, int32_t count, hipStrea
         return DTB_ERR_HIP;
     if (hipEventRecord(b->ev[s], st) != hipSuccess) return DTB_ERR_HIP;
     if (hipGraphLaunch(b->exec, st) != hipSuccess) return DTB_ERR_HIP;
+    if (hipEventRecord(b->done, st) != hipSuccess) return DTB_ERR_HIP;
+    b->last_stream = st;
+    b->has_run = true;
     return DTB_OK;
 }
 
@@ -967,10 +1175,10 @@ dtb_status dtb_plan_describe(dtb_plan_t p, int64_t* v, int32_t n)
 {
     if (!p || (n > 0 && !v) || n < 0) return DTB_ERR_INVALID_ARG;
     const Layout& L = p->layout;
-    const bool sw = p->path == DTB_PATH_SWEEP;
-    const int64_t all[] = {p->path, sw ? p->nwg_launch : L.nwg, L.k, sw ? p->sweep.D : 0, L.ER, L.EC,
+    const bool sw = p->path == DTB_PATH_SWEEP, ov = p->path == DTB_PATH_OVERLAPPED;
+    const int64_t all[] = {p->path, sw ? p->nwg_launch : L.nwg, ov ? 0 : L.k, sw ? p->sweep.D : (ov ? p->ovl_D : 0), L.ER, L.EC,
                            L.rows.parts, L.cols.parts, L.R, L.C, sw ? (int64_t)p->sweep.tiles.size() : 0,
-                           p->fma ? 0 : 1, L.waves};
+                           p->fma ? 0 : 1, L.waves, p->grid_sync ? 1 : 0};
     for (int32_t i = 0; i < n && i < (int32_t)(sizeof(all) / sizeof(all[0])); ++i) v[i] = all[i];
     return DTB_OK;
 }
@@ -1048,9 +1256,19 @@ int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32
 
 int32_t dtb_test_batch(int32_t count, const int64_t* rows, const int64_t* cols, const int32_t* dtype,
                        const int64_t* T, int32_t r64, int32_t r32, int32_t n_slots, int32_t* jobs,
-                       int32_t* slot_lists, int32_t slot_lists_len)
+                       int32_t* slot_lists, int32_t slot_lists_len, int64_t* info)
 {
-    if (count < 1 || !rows || !cols || !dtype || !T || r64 < 1 || r32 < 1 || n_slots < 1) return -1;
+    if (count < 1 || !rows || !cols || !dtype || !T || r64 < 0 || r32 < 0 || n_slots < 1) return -1;
+    std::vector<TileInst> insts;
+    if (r64 == 0 && r32 == 0) {
+        TileInst list[kMaxBatchInsts];
+        int n = 0;
+        (void)batched_kernel(list, &n);
+        insts.assign(list, list + n);
+    } else {
+        if (r64 < 1 || r32 < 1) return -1;
+        insts = {TileInst{0, r64, 2}, TileInst{1, r32, 4}};
+    }
     std::vector<BatchSpec> specs(count);
     for (int i = 0; i < count; ++i) {
         if (rows[i] < 1 || cols[i] < 1 || T[i] < 0 || (dtype[i] != 0 && dtype[i] != 1)) return -1;
@@ -1061,12 +1279,17 @@ int32_t dtb_test_batch(int32_t count, const int64_t* rows, const int64_t* cols, 
         specs[i].dtype = dtype[i];
     }
     BatchPlan bp;
-    if (!plan_batch(specs, r64, r32, 8, n_slots, &bp)) return -1;
+    if (!plan_batch(specs, insts, 8, n_slots, &bp)) return -1;
+    if (info) {
+        info[0] = (int64_t)bp.makespan;
+        info[1] = batch_spin_limit(bp.makespan, kSpinLimit);
+    }
     if (jobs) {
         for (size_t j = 0; j < bp.jobs.size(); ++j) {
             const BatchJob& J = bp.jobs[j];
             const int32_t v[DTB_TEST_BATCH_STRIDE] = {J.prob, J.g, J.sweep ? 1 : 0, J.ntiles, J.D, J.nrounds,
-                                                      J.flag_base, J.table_off, (int32_t)J.start, (int32_t)J.dur};
+                                                      J.flag_base, J.table_off, (int32_t)J.start, (int32_t)J.dur,
+                                                      J.k, J.R, J.C};
             for (int i = 0; i < DTB_TEST_BATCH_STRIDE; ++i) jobs[j * DTB_TEST_BATCH_STRIDE + i] = v[i];
         }
     }

@@ -3,9 +3,9 @@
 
 namespace dtb {
 
-const void* pick_f32_r16(bool sweep, bool fma, bool colmask, bool rowcheck)
+const void* pick_f32_r16(int kind, bool fma, bool colmask, bool rowcheck)
 {
-    return pick_instance<float, 4, 16>(sweep, fma, colmask, rowcheck);
+    return pick_instance<float, 4, 16>(kind, fma, colmask, rowcheck);
 }
 
 }  // namespace dtb

@@ -3,9 +3,9 @@
 
 namespace dtb {
 
-const void* pick_f32_r24(bool sweep, bool fma, bool colmask, bool rowcheck)
+const void* pick_f32_r24(int kind, bool fma, bool colmask, bool rowcheck)
 {
-    return pick_instance<float, 4, 24>(sweep, fma, colmask, rowcheck);
+    return pick_instance<float, 4, 24, kDtbWaves, true>(kind, fma, colmask, rowcheck);
 }
 
 }  // namespace dtb

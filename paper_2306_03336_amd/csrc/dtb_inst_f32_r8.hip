@@ -3,9 +3,9 @@
 
 namespace dtb {
 
-const void* pick_f32_r8(bool sweep, bool fma, bool colmask, bool rowcheck)
+const void* pick_f32_r8(int kind, bool fma, bool colmask, bool rowcheck)
 {
-    return pick_instance<float, 4, 8>(sweep, fma, colmask, rowcheck);
+    return pick_instance<float, 4, 8, kDtbWaves, true>(kind, fma, colmask, rowcheck);
 }
 
 }  // namespace dtb

@@ -5,9 +5,9 @@
 
 namespace dtb {
 
-const void* pick_f64c4_r12(bool sweep, bool fma, bool colmask, bool rowcheck)
+const void* pick_f64c4_r12(int kind, bool fma, bool colmask, bool rowcheck)
 {
-    return pick_instance<double, 4, 12>(sweep, fma, colmask, rowcheck);
+    return pick_instance<double, 4, 12, kDtbWaves, true>(kind, fma, colmask, rowcheck);
 }
 
 }  // namespace dtb

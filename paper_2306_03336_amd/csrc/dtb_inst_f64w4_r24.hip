@@ -5,9 +5,9 @@
 
 namespace dtb {
 
-const void* pick_f64w4_r24(bool sweep, bool fma, bool colmask, bool rowcheck)
+const void* pick_f64w4_r24(int kind, bool fma, bool colmask, bool rowcheck)
 {
-    return pick_instance<double, 2, 24, 4>(sweep, fma, colmask, rowcheck);
+    return pick_instance<double, 2, 24, 4>(kind, fma, colmask, rowcheck);
 }
 
 }  // namespace dtb

@@ -48,7 +48,8 @@ struct ProbDesc {
     double coeffs[5];    // c, n, s, e, w
     uint64_t* timing;    // DTB_DEBUG_TIMING: kTimingSlots counters per workgroup, else null
     int32_t direct_xchg; // 1: exchange border strips lane by lane, never through the LDS staging area
-    int32_t pad_;
+    int32_t grid_sync;   // 1: a device-wide barrier at every exchange point instead of neighbour flags
+    uint32_t* bar;       // grid_sync: the barrier's counters (kBarrierSlots slots, reset before each launch)
 };
 
 // Per-workgroup phase timing (s_memrealtime ticks, 100 MHz): time in steps,
@@ -97,7 +98,14 @@ struct JobDesc {
     int32_t D;
     int32_t nrounds;
     int32_t sweep;
+    int32_t R, C;       // the register-tile instance: rows and columns per lane
     void* ws;
+};
+
+// A register-tile instance the batched kernel carries: precision (0 = FP64,
+// 1 = FP32), rows and columns per lane (8 waves per workgroup).
+struct TileInst {
+    int dtype = 0, R = 0, C = 0;
 };
 
 // Entry of a launch slot's work list: job index and the slot's member index in it.

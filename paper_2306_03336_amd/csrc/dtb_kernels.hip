@@ -152,7 +152,7 @@ hipError_t launch_copy_halo(int dtype, const void* src, void* dst, int64_t pitch
 // Instantiated DTB kernels (one translation unit each, dtb_inst_*.hip): FP64
 // with 2 columns per lane (R = 8, 16, 24) or 4 (R = 12), FP32 with 4, 8 waves
 // per workgroup, R rows per lane.
-#define DTB_DECLARE(NAME) const void* NAME(bool sweep, bool fma, bool colmask, bool rowcheck);
+#define DTB_DECLARE(NAME) const void* NAME(int kind, bool fma, bool colmask, bool rowcheck);
 DTB_DECLARE(pick_f64c4_r12)
 DTB_DECLARE(pick_f64w4_r24)
 DTB_DECLARE(pick_f64_r8)
@@ -164,14 +164,15 @@ DTB_DECLARE(pick_f32_r24)
 DTB_DECLARE(pick_f32_r28)
 #undef DTB_DECLARE
 
-static const void* dtb_kernel_any(bool sweep, int dtype, int R, int want_waves, bool fma, bool colmask,
-                                  bool rowcheck, int* C, int* waves)
+// kind: 0 resident, 1 tile-serial sweep, 2 overlapped per-workgroup blocking.
+static const void* dtb_kernel_any(int kind, int dtype, int R, int want_waves, bool fma, bool colmask, bool rowcheck,
+                                  int* C, int* waves)
 {
     if (want_waves == 4) {
         // Half-height workgroups, two per compute unit (resident path only).
         *waves = 4;
         *C = 2;
-        if (!sweep && dtype == 0 && R == 24) return pick_f64w4_r24(sweep, fma, colmask, rowcheck);
+        if (kind == 0 && dtype == 0 && R == 24) return pick_f64w4_r24(kind, fma, colmask, rowcheck);
         return nullptr;
     }
     if (want_waves != 0 && want_waves != 8) return nullptr;
@@ -179,19 +180,19 @@ static const void* dtb_kernel_any(bool sweep, int dtype, int R, int want_waves, 
     if (dtype == 0) {
         *C = 2;
         switch (R) {
-        case 8: return pick_f64_r8(sweep, fma, colmask, rowcheck);
-        case 16: return pick_f64_r16(sweep, fma, colmask, rowcheck);
-        case 24: return pick_f64_r24(sweep, fma, colmask, rowcheck);
-        case 12: *C = 4; return pick_f64c4_r12(sweep, fma, colmask, rowcheck);
+        case 8: return pick_f64_r8(kind, fma, colmask, rowcheck);
+        case 16: return pick_f64_r16(kind, fma, colmask, rowcheck);
+        case 24: return pick_f64_r24(kind, fma, colmask, rowcheck);
+        case 12: *C = 4; return pick_f64c4_r12(kind, fma, colmask, rowcheck);
         default: return nullptr;
         }
     } else {
         *C = 4;
         switch (R) {
-        case 8: return pick_f32_r8(sweep, fma, colmask, rowcheck);
-        case 16: return pick_f32_r16(sweep, fma, colmask, rowcheck);
-        case 24: return pick_f32_r24(sweep, fma, colmask, rowcheck);
-        case 28: return pick_f32_r28(sweep, fma, colmask, rowcheck);
+        case 8: return pick_f32_r8(kind, fma, colmask, rowcheck);
+        case 16: return pick_f32_r16(kind, fma, colmask, rowcheck);
+        case 24: return pick_f32_r24(kind, fma, colmask, rowcheck);
+        case 28: return pick_f32_r28(kind, fma, colmask, rowcheck);
         default: return nullptr;
         }
     }
@@ -199,12 +200,17 @@ static const void* dtb_kernel_any(bool sweep, int dtype, int R, int want_waves, 
 
 const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves, int want_waves)
 {
-    return dtb_kernel_any(false, dtype, R, want_waves, fma, colmask, rowcheck, C, waves);
+    return dtb_kernel_any(0, dtype, R, want_waves, fma, colmask, rowcheck, C, waves);
 }
 
 const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
 {
-    return dtb_kernel_any(true, dtype, R, 8, fma, colmask, rowcheck, C, waves);
+    return dtb_kernel_any(1, dtype, R, 8, fma, colmask, rowcheck, C, waves);
+}
+
+const void* dtb_ovl_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
+{
+    return dtb_kernel_any(2, dtype, R, 8, fma, colmask, rowcheck, C, waves);
 }
 
 hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st)

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dtb_internal.h"
+
 namespace dtb {
 
 hipError_t launch_step(int dtype, bool fma, const void* in, void* out, int64_t pitch, int rows, int cols,
@@ -32,9 +34,17 @@ struct SweepArgs {
 
 hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st);
 
+// The overlapped per-workgroup blocking kernel of the same instance
+// (arguments: ProbDesc, descriptor table, source buffer, destination buffer,
+// steps), or nullptr where it is not instantiated (FP64 2 x 8, 2 x 24, 4 x 12;
+// FP32 4 x 8, 4 x 24).
+const void* dtb_ovl_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves);
+
 // The batched persistent kernel (arguments: ProbDesc*, JobDesc*, WgDesc*
 // table, work-list offsets, work items, flags, error word, spin limit); the
-// rows per lane it uses for each precision.
-const void* batched_kernel(int* rows_per_lane_f64, int* rows_per_lane_f32);
+// register-tile instances it carries (at most kMaxBatchInsts) into insts,
+// their number into *n.
+constexpr int kMaxBatchInsts = 8;
+const void* batched_kernel(TileInst* insts, int* n);
 
 }  // namespace dtb

@@ -17,47 +17,43 @@ int64_t axis_capacity(int ext, int k, int parts)
     return 2 * edge + (int64_t)(parts - 2) * std::max<int64_t>(inner, 0);
 }
 
-bool split_axis(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int parts, AxisSplit* out)
+bool split_axis_core(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int parts, int* bounds, int* ext0,
+                     bool* narrow)
 {
     const int64_t len = hi - lo;
     if (len < 1 || lo < 1 || hi > dom + 1 || ext < 1 || k < 1 || parts < 1 || parts > len) return false;
-    AxisSplit s;
-    s.parts = parts;
-    s.bounds.assign(parts + 1, 0);
-    s.ext0.assign(parts, 1);
-    s.narrow = dom < ext;
-    if (s.narrow) {
+    *narrow = dom < ext;
+    if (*narrow) {
         // The whole interior fits in one extended tile placed at its start.
         if (parts != 1 || lo != 1 || hi != dom + 1) return false;
-        s.bounds[0] = 1;
-        s.bounds[1] = (int)dom + 1;
-        s.ext0[0] = 1;
-        *out = s;
+        bounds[0] = 1;
+        bounds[1] = (int)dom + 1;
+        ext0[0] = 1;
         return true;
     }
     // Capacities: an end tile of the range needs a ghost ring on one side only.
-    std::vector<int64_t> cap(parts), w(parts, 0);
-    for (int i = 0; i < parts; ++i) {
+    auto cap = [&](int i) -> int64_t {
         const int sides = (parts == 1) ? 0 : ((i == 0 || i == parts - 1) ? 1 : 2);
-        cap[i] = ext - (int64_t)sides * k;
-        if (cap[i] < 1) return false;
-    }
-    // Even split, then hand the remainder to tiles with room, ends first.
+        return ext - (int64_t)sides * k;
+    };
+    for (int i = 0; i < parts; ++i)
+        if (cap(i) < 1) return false;
+    // Even split, then hand the remainder to tiles with room, ends first
+    // (order 0, parts - 1, 1, 2, ...).  The widths are kept in ext0 until the
+    // bounds are known.
+    int* w = ext0;
     const int64_t q = len / parts;
     int64_t left = len;
     for (int i = 0; i < parts; ++i) {
-        w[i] = std::min<int64_t>(q, cap[i]);
+        w[i] = (int)std::min<int64_t>(q, cap(i));
         left -= w[i];
     }
-    std::vector<int> order;
-    order.push_back(0);
-    if (parts > 1) order.push_back(parts - 1);
-    for (int i = 1; i < parts - 1; ++i) order.push_back(i);
+    auto order = [&](int j) { return j == 0 ? 0 : (j == 1 ? parts - 1 : j - 1); };
     while (left > 0) {
         bool moved = false;
-        for (int i : order) {
-            if (left == 0) break;
-            if (w[i] < cap[i]) {
+        for (int j = 0; j < parts && left > 0; ++j) {
+            const int i = order(j);
+            if (w[i] < cap(i)) {
                 ++w[i];
                 --left;
                 moved = true;
@@ -65,18 +61,41 @@ bool split_axis(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int parts, 
         }
         if (!moved) return false;
     }
-    s.bounds[0] = (int)lo;
-    for (int i = 0; i < parts; ++i) s.bounds[i + 1] = s.bounds[i] + (int)w[i];
+    bounds[0] = (int)lo;
     for (int i = 0; i < parts; ++i) {
         if (w[i] < 1) return false;
-        const int64_t o0 = s.bounds[i], o1 = s.bounds[i + 1];
+        bounds[i + 1] = bounds[i] + w[i];
+    }
+    for (int i = 0; i < parts; ++i) {
+        const int64_t o0 = bounds[i], o1 = bounds[i + 1];
         const int64_t f0 = std::max<int64_t>(o0 - k, lo), f1 = std::min<int64_t>(o1 + k, hi);
         const int64_t e0 = std::min<int64_t>(std::max<int64_t>(f0, 1), dom - ext + 1);
         if (f0 < e0 || f1 > e0 + ext) return false;
-        s.ext0[i] = (int)e0;
+        ext0[i] = (int)e0;
     }
-    *out = s;
     return true;
+}
+
+bool split_axis(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int parts, AxisSplit* out)
+{
+    if (parts < 1 || parts > hi - lo) return false;
+    AxisSplit s;
+    s.parts = parts;
+    s.bounds.assign(parts + 1, 0);
+    s.ext0.assign(parts, 1);
+    if (!split_axis_core(lo, hi, dom, ext, k, parts, s.bounds.data(), s.ext0.data(), &s.narrow)) return false;
+    *out = std::move(s);
+    return true;
+}
+
+int first_parts_guess(int64_t len, int ext, int k)
+{
+    const int64_t inner = ext - 2 * k, edge = ext - k;
+    if (edge < 1) return 0;
+    if (len <= ext) return 1;
+    if (len <= 2 * edge) return 2;
+    if (inner < 1) return 0;
+    return (int)std::min<int64_t>(2 + (len - 2 * edge + inner - 1) / inner, INT_MAX);
 }
 
 int min_parts(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int max_parts)
@@ -85,41 +104,17 @@ int min_parts(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int max_parts
     if (len < 1) return 0;
     AxisSplit s;
     if (len <= ext && split_axis(lo, hi, dom, ext, k, 1, &s)) return 1;
-    int64_t p = 2;
-    const int64_t inner = ext - 2 * k, edge = ext - k;
-    if (edge < 1) return 0;
-    if (len > 2 * edge) {
-        if (inner < 1) return 0;
-        p = 2 + (len - 2 * edge + inner - 1) / inner;
-    }
+    int64_t p = std::max(first_parts_guess(len, ext, k), 2);
+    if (first_parts_guess(len, ext, k) == 0) return 0;
     for (; p <= max_parts && p <= len; ++p) {
         if (split_axis(lo, hi, dom, ext, k, (int)p, &s)) return (int)p;
     }
     return 0;
 }
 
-bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st, int R, int C, int waves, int k,
-                  int n_xcd, int wg_base, int prob, Layout* out)
+void xcd_slot_order(int pr, int pc, const Region& cr, int n_xcd, int wg_base, int* slot_of_tile, int* scratch)
 {
-    Layout L;
-    L.R = R;
-    L.C = C;
-    L.waves = waves;
-    L.ER = waves * R;
-    L.EC = kWaveSize * C;
-    L.k = k;
-    const int pr = min_parts(cr.r0, cr.r1, rows, L.ER, k, 1 << 20);
-    const int pc = min_parts(cr.c0, cr.c1, cols, L.EC, k, 1 << 20);
-    if (pr < 1 || pc < 1) return false;
-    if (!split_axis(cr.r0, cr.r1, rows, L.ER, k, pr, &L.rows) ||
-        !split_axis(cr.c0, cr.c1, cols, L.EC, k, pc, &L.cols))
-        return false;
     const int n = pr * pc;
-    L.nwg = n;
-
-    // Spatial order: cut the pr x pc tile grid into gy x gx blocks (gy * gx =
-    // n_xcd, blocks as square as possible in cells), list the tiles block by
-    // block, row-major inside each block.
     int gy = 1, gx = 1;
     if (n_xcd > 1) {
         double best = 1e300;
@@ -136,25 +131,46 @@ bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st
             }
         }
     }
-    std::vector<int> spatial;  // tile id = tr * pc + tc, in XCD-block order
-    spatial.reserve(n);
+    // scratch: the tiles (id tr * pc + tc) in XCD-block order.
+    int m = 0;
     for (int by = 0; by < gy; ++by) {
         const int r0 = (int)((int64_t)pr * by / gy), r1 = (int)((int64_t)pr * (by + 1) / gy);
         for (int bx = 0; bx < gx; ++bx) {
             const int c0 = (int)((int64_t)pc * bx / gx), c1 = (int)((int64_t)pc * (bx + 1) / gx);
             for (int tr = r0; tr < r1; ++tr)
-                for (int tc = c0; tc < c1; ++tc) spatial.push_back(tr * pc + tc);
+                for (int tc = c0; tc < c1; ++tc) scratch[m++] = tr * pc + tc;
         }
     }
-    // Workgroup b of the launch runs on XCD (wg_base + b) % n_xcd; list the
-    // launch slots XCD by XCD and give them the tiles in spatial order.
-    std::vector<int> slots(n);
-    for (int b = 0; b < n; ++b) slots[b] = b;
+    // Launch slots XCD by XCD (slot order kept within an XCD), matched to the tiles in that order.
     const int nx = std::max(n_xcd, 1);
-    std::stable_sort(slots.begin(), slots.end(),
-                     [&](int x, int y) { return (wg_base + x) % nx < (wg_base + y) % nx; });
-    std::vector<int> slot_of_tile(n);
-    for (int i = 0; i < n; ++i) slot_of_tile[spatial[i]] = slots[i];
+    int i = 0;
+    for (int x = 0; x < nx; ++x)
+        for (int b = 0; b < n; ++b)
+            if ((wg_base + b) % nx == x) slot_of_tile[scratch[i++]] = b;
+}
+
+bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st, int R, int C, int waves, int k,
+                  int n_xcd, int wg_base, int prob, Layout* out, bool neighbours, int max_tiles)
+{
+    Layout L;
+    L.R = R;
+    L.C = C;
+    L.waves = waves;
+    L.ER = waves * R;
+    L.EC = kWaveSize * C;
+    L.k = k;
+    const int pr = min_parts(cr.r0, cr.r1, rows, L.ER, k, 1 << 20);
+    const int pc = min_parts(cr.c0, cr.c1, cols, L.EC, k, 1 << 20);
+    if (pr < 1 || pc < 1) return false;
+    if ((int64_t)pr * pc > max_tiles) return false;
+    if (!split_axis(cr.r0, cr.r1, rows, L.ER, k, pr, &L.rows) ||
+        !split_axis(cr.c0, cr.c1, cols, L.EC, k, pc, &L.cols))
+        return false;
+    const int n = pr * pc;
+    L.nwg = n;
+
+    std::vector<int> slot_of_tile(n), scratch(n);
+    xcd_slot_order(pr, pc, cr, n_xcd, wg_base, slot_of_tile.data(), scratch.data());
 
     L.wgs.assign(n, WgDesc{});
     for (int tr = 0; tr < pr; ++tr) {
@@ -178,16 +194,30 @@ bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st
             d.nnb = 0;
         }
     }
-    for (int a = 0; a < n; ++a) {
-        WgDesc& d = L.wgs[a];
-        const int f_r0 = d.own_r0 - k, f_r1 = d.own_r1 + k, f_c0 = d.own_c0 - k, f_c1 = d.own_c1 + k;
-        for (int b = 0; b < n; ++b) {
-            if (b == a) continue;
-            const WgDesc& o = L.wgs[b];
-            const bool meet = o.own_r0 < f_r1 && o.own_r1 > f_r0 && o.own_c0 < f_c1 && o.own_c1 > f_c0;
-            if (!meet) continue;
-            if (d.nnb >= kMaxNeighbours) return false;
-            d.nb[d.nnb++] = wg_base + b;
+    // Neighbours: the tiles whose owned cells lie within k of a tile's owned
+    // cells.  Owned ranges along an axis are consecutive, so they sit in a
+    // contiguous run of tile rows and of tile columns around the tile's own;
+    // listed in launch-slot order.
+    if (neighbours) {
+        std::vector<int> nbs;
+        for (int tr = 0; tr < pr; ++tr) {
+            int r_lo = tr, r_hi = tr;
+            while (r_lo > 0 && L.rows.bounds[r_lo] > L.rows.bounds[tr] - k) --r_lo;        // bounds[r_lo] is tile r_lo's end
+            while (r_hi + 1 < pr && L.rows.bounds[r_hi + 1] < L.rows.bounds[tr + 1] + k) ++r_hi;
+            for (int tc = 0; tc < pc; ++tc) {
+                int c_lo = tc, c_hi = tc;
+                while (c_lo > 0 && L.cols.bounds[c_lo] > L.cols.bounds[tc] - k) --c_lo;
+                while (c_hi + 1 < pc && L.cols.bounds[c_hi + 1] < L.cols.bounds[tc + 1] + k) ++c_hi;
+                WgDesc& d = L.wgs[slot_of_tile[tr * pc + tc]];
+                nbs.clear();
+                for (int ur = r_lo; ur <= r_hi; ++ur)
+                    for (int uc = c_lo; uc <= c_hi; ++uc)
+                        if (ur != tr || uc != tc) nbs.push_back(wg_base + slot_of_tile[ur * pc + uc]);
+                if ((int)nbs.size() > kMaxNeighbours) return false;
+                std::sort(nbs.begin(), nbs.end());
+                d.nnb = (int)nbs.size();
+                for (int i = 0; i < d.nnb; ++i) d.nb[i] = nbs[i];
+            }
         }
     }
     *out = std::move(L);
@@ -195,15 +225,16 @@ bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st
 }
 
 // Fitted to per-workgroup phase clocks at 2048^2 (FP64) and 1536^2 / 3072^2
-// (FP32): a step costs about 54 ps per FP64 cell and 39 ps per FP32 cell
-// (VALU-bound: wave64 FP64 and FP32 instructions at 16 and 32 lanes per
+// (FP32): a step costs about 52 ps per FP64 cell with 4 columns per lane, 56 ps
+// with 2 (two cross-lane moves per cell instead of one), and 39 ps per FP32
+// cell (VALU-bound: wave64 FP64 and FP32 instructions at 16 and 32 lanes per
 // clock per SIMD) plus the per-step barrier; an exchange costs a few
 // microseconds of fixed latency (store completion, flag round trip, load
 // latency) plus a part that grows with the number of border cells moved
 // lane by lane.
 double tile_step_time_us(int ER, int EC, int elem_bytes)
 {
-    const double per_cell = elem_bytes == 8 ? 54e-6 : 39e-6;
+    const double per_cell = elem_bytes == 8 ? (EC <= 2 * kWaveSize ? 56e-6 : 52e-6) : 39e-6;
     return (double)ER * EC * per_cell + 0.11;
 }
 
@@ -216,12 +247,17 @@ double exchange_time_us(int ER, int EC, int R, int C, int elem_bytes, bool stage
 
 double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes)
 {
+    return layout_cost_of(L.nwg, L.R, L.C, L.ER, L.EC, L.k, slots_per_cu, n_cu, elem_bytes);
+}
+
+double layout_cost_of(int nwg, int R, int C, int ER, int EC, int k, int slots_per_cu, int n_cu, int elem_bytes)
+{
     const int slots = std::max(1, slots_per_cu) * std::max(1, n_cu);
-    if (L.nwg > slots) return 1e300;
-    const int per_cu = (L.nwg + n_cu - 1) / n_cu;
-    const bool staged = exchange_staged(L.R, L.C, elem_bytes, L.k);
-    const double step = tile_step_time_us(L.ER, L.EC, elem_bytes);
-    const double exch = exchange_time_us(L.ER, L.EC, L.R, L.C, elem_bytes, staged) / L.k;
+    if (nwg > slots) return 1e300;
+    const int per_cu = (nwg + n_cu - 1) / n_cu;
+    const bool staged = exchange_staged(R, C, elem_bytes, k);
+    const double step = tile_step_time_us(ER, EC, elem_bytes);
+    const double exch = exchange_time_us(ER, EC, R, C, elem_bytes, staged) / k;
     if (per_cu <= 1) return step + exch;
     // Several workgroups per compute unit: measured (2048^2 FP64, two
     // half-height workgroups per unit), their exchanges hardly overlap the
@@ -289,7 +325,7 @@ bool plan_sweep(int64_t rows, int64_t cols, int R, int C, int waves, int k, int 
             Region cr{std::max(st.r0 - D, 1), std::min<int>(st.r1 + D, (int)rows + 1), std::max(st.c0 - D, 1),
                       std::min<int>(st.c1 + D, (int)cols + 1)};
             Layout L;
-            if (!build_layout(rows, cols, cr, st, R, C, waves, k, n_xcd, 0, 0, &L)) return false;
+            if (!build_layout(rows, cols, cr, st, R, C, waves, k, n_xcd, 0, 0, &L, true, max_wg)) return false;
             if (L.nwg > max_wg) return false;
             P.nwg = std::max(P.nwg, L.nwg);
             P.tiles.push_back(std::move(L));
@@ -327,79 +363,109 @@ double tile_step_us(int ER, int EC, int elem_bytes, int active_rows)
     return tile_step_time_us(rows, EC, elem_bytes);
 }
 
-bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves, int nslots, BatchPlan* out)
+bool plan_batch(const std::vector<BatchSpec>& probs, const std::vector<TileInst>& insts, int waves, int nslots,
+                BatchPlan* out)
 {
     if (nslots < 1 || waves < 1) return false;
     BatchPlan bp;
     bp.nslots = nslots;
     const double t_bar = 5.0;  // device-wide barrier between sweep rounds
+    // Every candidate of every problem: the job (without flags and table
+    // offset) and its descriptor table (neighbours numbered from 0).
+    struct Cand {
+        BatchJob J;
+        std::vector<WgDesc> tab;
+    };
+    std::vector<std::vector<Cand>> cands(probs.size());
+    for (int p = 0; p < (int)probs.size(); ++p) {
+        const BatchSpec& q = probs[p];
+        const int eb = q.dtype == 0 ? 8 : 4;
+        for (int ii = 0; ii < (int)insts.size(); ++ii) {
+            const TileInst& ti = insts[ii];
+            if (ti.dtype != q.dtype) continue;
+            const int R = ti.R, C = ti.C, ER = waves * R, EC = kWaveSize * C;
+            BatchJob base;
+            base.prob = p;
+            base.inst = ii;
+            base.R = R;
+            base.C = C;
+            base.narrow_cols = q.cols < EC;
+            base.narrow_rows = q.rows < ER;
+            bool resident = false;
+            for (int k = 1; k <= 16; ++k) {
+                Layout L;
+                if (!build_layout(q.rows, q.cols, interior(q.rows, q.cols), interior(q.rows, q.cols), R, C, waves, k, 1,
+                                  0, p, &L, true, nslots))
+                    continue;
+                resident = true;
+                Cand c{base, std::move(L.wgs)};
+                c.J.sweep = false;
+                c.J.g = L.nwg;
+                c.J.k = k;
+                c.J.D = (int)std::min<int64_t>(q.T, INT32_MAX);
+                const int act = (int)std::min<int64_t>(q.rows, ER);
+                const double t_exch = exchange_time_us(ER, EC, R, C, eb, exchange_staged(R, C, eb, k));
+                const int64_t nexch = q.T > k ? (q.T + k - 1) / k - 1 : 1;
+                c.J.dur = q.T * tile_step_us(ER, EC, eb, act) + (double)nexch * t_exch;
+                cands[p].push_back(std::move(c));
+            }
+            if (resident) continue;
+            for (int k : {4, 6, 8, 10, 12}) {
+                for (int D : {16, 24, 32, 48, 64, 96, 128}) {
+                    SweepPlan sp;
+                    if (!plan_sweep(q.rows, q.cols, R, C, waves, k, D, nslots, 1, &sp)) continue;
+                    const int64_t nrounds = (q.T + D - 1) / D;
+                    if (nrounds > INT32_MAX) continue;
+                    const double t_exch = exchange_time_us(ER, EC, R, C, eb, exchange_staged(R, C, eb, k));
+                    const double per_tile = D * tile_step_us(ER, EC, eb, ER) + (double)D / k * t_exch + t_bar;
+                    Cand c{base, std::move(sp.table)};
+                    c.J.sweep = true;
+                    c.J.g = sp.nwg;
+                    c.J.k = k;
+                    c.J.D = D;
+                    c.J.ntiles = (int)sp.tiles.size();
+                    c.J.nrounds = (int)nrounds;
+                    c.J.dur = nrounds * per_tile * sp.tiles.size();
+                    for (WgDesc& d : c.tab) d.prob = p;
+                    cands[p].push_back(std::move(c));
+                }
+            }
+        }
+        if (cands[p].empty()) return false;
+    }
+    // The makespan cannot be shorter than the least total slot time spread
+    // over every slot, nor than any job's least duration.
+    double area = 0, longest = 0;
+    for (const auto& cs : cands) {
+        double a = 1e300, d = 1e300;
+        for (const Cand& c : cs) {
+            a = std::min(a, c.J.g * c.J.dur);
+            d = std::min(d, c.J.dur);
+        }
+        area += a;
+        longest = std::max(longest, d);
+    }
+    const double bound = std::max(area / nslots, longest);
     std::vector<BatchJob> jobs;
     std::vector<std::vector<WgDesc>> tables;
     int flag_base = 0;
     for (int p = 0; p < (int)probs.size(); ++p) {
-        const BatchSpec& q = probs[p];
-        const int R = q.dtype == 0 ? r64 : r32, C = q.dtype == 0 ? 2 : 4;
-        const int ER = waves * R, EC = kWaveSize * C;
-        const int eb = q.dtype == 0 ? 8 : 4;
-        BatchJob J;
-        J.prob = p;
-        J.narrow_cols = q.cols < EC;
-        J.narrow_rows = q.rows < ER;
-        std::vector<WgDesc> tab;
-        bool ok = false;
-        for (int k : {8, 6, 4, 2, 1}) {
-            Layout L;
-            if (build_layout(q.rows, q.cols, interior(q.rows, q.cols), interior(q.rows, q.cols), R, C, waves, k, 1,
-                             flag_base, 0, &L) &&
-                L.nwg <= nslots) {
-                J.sweep = false;
-                J.g = L.nwg;
-                J.k = k;
-                J.D = (int)std::min<int64_t>(q.T, INT32_MAX);
-                const int act = (int)std::min<int64_t>(q.rows, ER);
-                const double t_exch = exchange_time_us(ER, EC, R, C, eb, exchange_staged(R, C, eb, k));
-                J.dur = q.T * tile_step_us(ER, EC, eb, act) + (double)q.T / k * t_exch;
-                tab = L.wgs;
-                ok = true;
-                break;
-            }
+        int best = -1;
+        for (int i = 0; i < (int)cands[p].size(); ++i) {
+            const BatchJob& J = cands[p][i].J;
+            if (J.dur > bound * (1 + 1e-9)) continue;
+            if (best < 0 || J.g * J.dur < cands[p][best].J.g * cands[p][best].J.dur) best = i;
         }
-        if (!ok) {
-            double best = 1e300;
-            for (int k : {8, 4}) {
-                for (int D : {16, 32, 64, 128}) {
-                    SweepPlan sp;
-                    if (!plan_sweep(q.rows, q.cols, R, C, waves, k, D, nslots, 1, &sp)) continue;
-                    const int64_t nrounds = (q.T + D - 1) / D;
-                    const double t_exch = exchange_time_us(ER, EC, R, C, eb, exchange_staged(R, C, eb, k));
-                    const double per_tile = D * tile_step_us(ER, EC, eb, ER) + (double)D / k * t_exch + t_bar;
-                    const double dur = nrounds * per_tile * sp.tiles.size();
-                    if (dur < best) {
-                        best = dur;
-                        J.sweep = true;
-                        J.g = sp.nwg;
-                        J.k = k;
-                        J.D = D;
-                        J.ntiles = (int)sp.tiles.size();
-                        J.nrounds = (int)nrounds;
-                        J.dur = dur;
-                        tab = sp.table;
-                        ok = true;
-                    }
-                }
-            }
-            if (ok) {
-                for (WgDesc& d : tab) {
-                    for (int i = 0; i < d.nnb; ++i) d.nb[i] += flag_base;
-                    d.prob = p;
-                }
-            }
-        }
-        if (!ok) return false;
-        J.flag_base = flag_base;
-        flag_base += J.g;
-        jobs.push_back(std::move(J));
-        tables.push_back(std::move(tab));
+        if (best < 0)
+            for (int i = 0; i < (int)cands[p].size(); ++i)
+                if (best < 0 || cands[p][i].J.dur < cands[p][best].J.dur) best = i;
+        Cand& c = cands[p][best];
+        for (WgDesc& d : c.tab)
+            for (int i = 0; i < d.nnb; ++i) d.nb[i] += flag_base;
+        c.J.flag_base = flag_base;
+        flag_base += c.J.g;
+        jobs.push_back(std::move(c.J));
+        tables.push_back(std::move(c.tab));
     }
     bp.nflags = flag_base;
 

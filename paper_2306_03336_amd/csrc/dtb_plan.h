@@ -36,8 +36,24 @@ struct AxisSplit {
 // the interior.  Returns false if that is impossible.
 bool split_axis(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int parts, AxisSplit* out);
 
+// The same split written into caller-provided arrays (bounds: parts + 1
+// entries, ext0: parts); allocates nothing.
+bool split_axis_core(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int parts, int* bounds, int* ext0,
+                     bool* narrow);
+
 // Smallest feasible number of parts (or 0 if none up to max_parts).
 int min_parts(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int max_parts);
+
+// Lower bound on the parts an axis of len cells needs (0: none can hold it).
+int first_parts_guess(int64_t len, int ext, int k);
+
+// Launch slot of every tile of a pr x pc tile grid covering the region cr:
+// the tile grid is cut into gy x gx blocks (gy * gx = n_xcd, blocks as square
+// as possible in cells), the tiles are listed block by block (row-major inside
+// a block), and the launch slots XCD by XCD (workgroup b runs on XCD
+// (wg_base + b) % n_xcd) receive them in that order.  slot_of_tile and
+// scratch: pr * pc entries each; allocates nothing.
+void xcd_slot_order(int pr, int pc, const Region& cr, int n_xcd, int wg_base, int* slot_of_tile, int* scratch);
 
 // Largest range one axis of `parts` tiles can cover.
 int64_t axis_capacity(int ext, int k, int parts);
@@ -55,9 +71,11 @@ struct Layout {
 // n_xcd), and for every tile the list of tiles within k of it.  wg_base
 // offsets every workgroup index (several problems in one launch); prob is
 // stored in each descriptor.  Returns false if no layout exists or a
-// neighbour list overflows.
+// neighbour list overflows.  neighbours = false leaves the lists empty
+// (layouts whose workgroups never wait for each other).  A layout of more
+// than max_tiles tiles is not built (returns false).
 bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st, int R, int C, int waves, int k,
-                  int n_xcd, int wg_base, int prob, Layout* out);
+                  int n_xcd, int wg_base, int prob, Layout* out, bool neighbours = true, int max_tiles = INT32_MAX);
 
 // The whole interior as computed and stored region.
 inline Region interior(int64_t rows, int64_t cols) { return Region{1, (int)rows + 1, 1, (int)cols + 1}; }
@@ -74,6 +92,7 @@ double exchange_time_us(int ER, int EC, int R, int C, int elem_bytes, bool stage
 // all their steps, and one exchange every k steps (the exchanges of
 // co-resident tiles overlap).  Infinite if the layout does not fit.
 double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes);
+double layout_cost_of(int nwg, int R, int C, int ER, int EC, int k, int slots_per_cu, int n_cu, int elem_bytes);
 
 // ---- tile-serial sweep
 
@@ -102,6 +121,8 @@ struct BatchSpec {
 
 struct BatchJob {
     int prob = 0;
+    int inst = 0;              // index into the planner's instance list
+    int R = 0, C = 0;
     bool sweep = false;
     int g = 0;                 // workgroups of the group
     int k = 0, D = 0, ntiles = 1, nrounds = 1;
@@ -124,13 +145,32 @@ struct BatchPlan {
 // `active_rows` rows hold grid rows (rows outside the grid are skipped).
 double tile_step_us(int ER, int EC, int elem_bytes, int active_rows);
 
-// Plan a batch: every problem becomes a job on a group of workgroups (held
-// on chip if it fits nslots tiles, else swept through big tiles), the jobs
-// are list-scheduled longest first onto nslots launch slots, and every slot
-// gets its (job, member) work list in one global job order.  FP64 problems
-// use 2 x r64 cells per lane, FP32 4 x r32.  Returns false if a problem fits
-// no layout.
-bool plan_batch(const std::vector<BatchSpec>& probs, int r64, int r32, int waves, int nslots, BatchPlan* out);
+// Plan a batch.  Every problem becomes a job on a group of workgroups, chosen
+// per problem among the instances of its precision, every exchange depth k
+// and (for a grid larger than nslots tiles) every tile-serial round depth D:
+// held on chip if it fits nslots tiles, else swept through big tiles.  Of a
+// problem's candidates the planner takes the one with the least slot time
+// (workgroups x modelled duration) among those no longer than the batch's
+// lower bound on the makespan (the larger of the least total slot time over
+// nslots and the longest least duration), else the shortest.  The jobs are
+// then list-scheduled longest first onto the nslots launch slots, and every
+// slot gets its (job, member) work list in one global job order.  Returns
+// false if a problem fits no layout.
+bool plan_batch(const std::vector<BatchSpec>& probs, const std::vector<TileInst>& insts, int waves, int nslots,
+                BatchPlan* out);
+
+// Poll limit of the batched kernel's bounded waits.  Under the list schedule a
+// member may legitimately wait at its job's first synchronisation point for
+// the rest of an earlier job on another member's slot -- up to the whole
+// modelled makespan.  A poll takes at least one s_sleep (64 clocks, 27 ns at
+// 2.4 GHz); the limit covers 8 times the modelled makespan at that rate, and
+// never less than `floor` polls.
+inline uint32_t batch_spin_limit(double makespan_us, uint32_t floor)
+{
+    const double polls = makespan_us * 8.0 / 0.027;
+    if (!(polls > floor)) return floor;
+    return polls >= 4.0e9 ? 4000000000u : (uint32_t)polls;
+}
 
 // Exchange points run_epochs performs for a segment of `steps` steps.
 inline int exchanges_per_segment(int64_t steps, int k)

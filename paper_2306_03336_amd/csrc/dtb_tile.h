@@ -39,31 +39,19 @@ namespace dtb {
 
 // ============================================================================ deep temporal blocking
 
-// How border strips travel between workgroups.  0: device-scope (sc1) stores
-// and loads, ordered by s_waitcnt; 1: plain (L2-cached) stores and loads with
-// one agent-scope release (L2 write-back) / acquire (L2 invalidate) per
-// workgroup per exchange.
-#ifndef DTB_XCHG_MODE
-#define DTB_XCHG_MODE 0
-#endif
-
+// Border strips travel between workgroups with device-scope (sc1) relaxed
+// atomic stores and loads, which are coherent across XCDs without an L2
+// write-back or invalidate; their order is enforced by s_waitcnt at the
+// exchange point.
 template <typename T>
 __device__ __forceinline__ void xchg_store(T* p, T v)
 {
-#if DTB_XCHG_MODE == 0
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#else
-    *p = v;
-#endif
 }
 template <typename T>
 __device__ __forceinline__ T xchg_load(T* p)
 {
-#if DTB_XCHG_MODE == 0
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#else
-    return *p;
-#endif
 }
 
 // DPP wave shifts (GFX9 wave_shr:1 / wave_shl:1) with bound_ctrl: a lane
@@ -223,6 +211,8 @@ struct Tile {
     using G = Geo<T, C, R, WAVES>;
     static constexpr int ER = G::ER;
     static constexpr int EC = G::EC;
+    static constexpr int kWaves = WAVES;
+    static constexpr bool kColmask = COLMASK;
     // Some cells are never written by a step (those outside the grid).
     static constexpr bool kKeepsCells = COLMASK || ROWCHECK;
     using LdsT = __attribute__((address_space(3))) T;  // a cell addressed by its LDS byte address
@@ -643,9 +633,6 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-#if DTB_XCHG_MODE == 1
-    if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-#endif
     if (threadIdx.x == 0) __hip_atomic_store(flags + (size_t)me * kFlagStride, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((int)threadIdx.x < d.nnb) {
         const int nb = d.nb[threadIdx.x];
@@ -660,11 +647,68 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
             if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         }
     }
-#if DTB_XCHG_MODE == 1
-    if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#endif
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+}
+
+// Device-wide barrier for the sweep, two levels deep so that no address has
+// more than one XCD's workgroups polling it.  Counters (each in its own
+// kFlagStride slot, all reset to 0 before the launch): slot 0 counts XCDs,
+// slots 1..8 count arrivals per XCD, slots 9..16 are per-XCD release words.
+// Workgroup b runs on XCD b % 8.  Barrier number n (1-based): the last
+// arrival of an XCD bumps the XCD counter, waits for every XCD, then releases
+// its own XCD by writing n.  Prior device-scope stores are complete (vmcnt 0)
+// before arriving.  Bounded waits as in exchange_point.
+constexpr int kBarrierSlots = 17;
+
+__device__ __forceinline__ bool spin_until(uint32_t* p, uint32_t target, int* err, int code, uint32_t spin_limit)
+{
+    uint32_t spins = 0;
+    while (!reached(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > spin_limit) {
+            __hip_atomic_fetch_or(err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err, uint32_t spin_limit)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t x = blockIdx.x % 8u;
+        const uint32_t per_xcd = (gridDim.x - x + 7u) / 8u;  // workgroups on this XCD
+        const uint32_t nxcd = gridDim.x < 8u ? gridDim.x : 8u;
+        uint32_t* xcnt = bar + (size_t)(1 + x) * kFlagStride;
+        uint32_t* xrel = bar + (size_t)(9 + x) * kFlagStride;
+        const uint32_t old = __hip_atomic_fetch_add(xcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == per_xcd * n) {
+            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            spin_until(bar, nxcd * n, err, 2, spin_limit);
+            __hip_atomic_store(xrel, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        spin_until(xrel, n, err, 2, spin_limit);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
+// The synchronisation at an exchange point: by default each workgroup waits
+// for the workgroups whose cells it reads (neighbour epoch flags); with
+// P.grid_sync every workgroup waits for all of them at a device-wide barrier
+// (the bulk-synchronous grid barrier of Section 3.2, kept to measure what the
+// neighbour-wise form is worth).  `epoch` counts this run's exchange points
+// from 1, which is also the barrier's number (its counters are reset before
+// every launch).
+__device__ __forceinline__ void sync_point(const ProbDesc& P, uint32_t* flags, int me, const WgDesc& d, uint32_t base,
+                                           uint32_t epoch, int* err, uint32_t spin_limit)
+{
+    if (P.grid_sync) grid_barrier(P.bar, epoch, err, spin_limit);
+    else exchange_point(flags, me, d, base + epoch, err, spin_limit);
 }
 
 // All time steps of one tile, the halo addends either fixed (HALO_ROWS =
@@ -746,7 +790,7 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
                 t0 = t1;
             }
             ++epoch;
-            exchange_point(flags, me, d, base + epoch, err, spin_limit);
+            sync_point(P, flags, me, d, base, epoch, err, spin_limit);
             if (timing) {
                 const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
                 tm[kTimeWait] += t1 - t0;
@@ -807,24 +851,22 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
     // result goes back in place, make sure they all have before it is written.
     if (!exchanged) {
         ++epoch;
-        exchange_point(flags, me, d, base + epoch, err, spin_limit);
+        sync_point(P, flags, me, d, base, epoch, err, spin_limit);
     }
 }
 
-// One segment of work for one workgroup: load its extended tile from src,
-// advance it `steps` steps (exchanging every k), store its owned cells inside
-// the stored region to dst.  SWEEP: src/dst are the sweep's HBM buffers, read
-// and written with device-scope accesses (other XCDs wrote / will read them
-// inside the same launch).
-template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS, bool SWEEP,
-          bool STAGED = true>
-__device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int64_t steps,
-                                            int me, uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
-                                            uint32_t spin_limit, char* lds)
+// Load a workgroup's extended tile from src into both register sets, the
+// rows just above and below it into the LDS edge slots and the west/east halo
+// products into LDS, and set up the tile's per-lane constants.  SC1: src is
+// read with device-scope loads (other XCDs wrote it inside the same launch).
+template <bool SC1, typename Tl, typename T>
+__device__ __forceinline__ void load_tile(Tl& t, const ProbDesc& P, const WgDesc& d, const T* src, char* lds)
 {
-    using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>;
     using G = typename Tl::G;
-    Tl t;
+    constexpr int C = G::EC / kWaveSize;
+    constexpr int R = G::ER / (Tl::kWaves);
+    constexpr int WAVES = Tl::kWaves;
+    constexpr bool COLMASK = Tl::kColmask;
     const T* grid = src;
     const int64_t pitch = P.pitch;
     const int rows = P.rows, cols = P.cols;
@@ -839,7 +881,7 @@ __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, 
 #pragma unroll
     for (int c = 0; c < C; ++c) t.colact[c] = (t.col0 + c) <= cols;
 
-    // ---- load the extended tile (both register sets) and the fixed boundary values
+    // ---- the extended tile (both register sets)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int g = t.g0 + r;
@@ -848,7 +890,7 @@ __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, 
             const int col = t.col0 + c;
             T v = T(0);
             if (g <= rows + 1 && col <= cols + 1) {
-                if constexpr (SWEEP)
+                if constexpr (SC1)
                     v = __hip_atomic_load(grid + (int64_t)g * pitch + col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 else
                     v = grid[(int64_t)g * pitch + col];
@@ -893,9 +935,51 @@ __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, 
     t.hbw = hx + (t.lane == 0 ? 0 : 2 * G::ER);
     t.hbe = hx + (t.lane == 63 ? G::ER : 2 * G::ER);
     t.hbwe = hx + (t.lane == 0 ? 0 : (t.lane == 63 ? G::ER : 2 * G::ER));
+}
 
+// One segment of work for one workgroup: load its extended tile from src,
+// advance it `steps` steps (exchanging every k), store its owned cells inside
+// the stored region to dst.  SWEEP: src/dst are the sweep's HBM buffers, read
+// and written with device-scope accesses (other XCDs wrote / will read them
+// inside the same launch).
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS, bool SWEEP,
+          bool STAGED = true>
+__device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int64_t steps,
+                                            int me, uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
+                                            uint32_t spin_limit, char* lds)
+{
+    using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>;
+    Tl t;
+    load_tile<SWEEP>(t, P, d, src, lds);
     run_epochs<HALO_ROWS, STAGED>(t, P, d, steps, me, flags, base, epoch, err, spin_limit);
-    t.template store_owned<SWEEP>(t.a, dst, pitch, d);
+    t.template store_owned<SWEEP>(t.a, dst, P.pitch, d);
+}
+
+// Overlapped (trapezoidal) temporal blocking of one workgroup, with no
+// synchronisation between workgroups at all: its extended tile is loaded from
+// src with a ring as deep as the number of steps, advanced `steps` steps
+// (after which the owned cells are exact: stale values from the tile's open
+// edges move one cell per step), and its owned cells are stored to dst.
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS>
+__device__ __forceinline__ void run_overlapped(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int steps,
+                                               char* lds)
+{
+    using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>;
+    Tl t;
+    load_tile<false>(t, P, d, src, lds);
+    const int rows = P.rows;
+    for (int s = 0; s + 1 < steps; s += 2) {
+        t.template step<HALO_ROWS>(t.a, t.b, 0, rows);
+        t.template step<HALO_ROWS>(t.b, t.a, 1, rows);
+    }
+    if (steps & 1) {
+        t.template step<HALO_ROWS>(t.a, t.b, 0, rows);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < C; ++c) t.a[r][c] = t.b[r][c];
+    }
+    t.template store_owned<false>(t.a, dst, P.pitch, d);
 }
 
 // Does the west or east halo of this tile's rows change from row to row?
@@ -946,50 +1030,21 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb(ProbDesc P, const WgDesc*
                                                                            epoch, err, spin_limit, lds);
 }
 
-// Device-wide barrier for the sweep, two levels deep so that no address has
-// more than one XCD's workgroups polling it.  Counters (each in its own
-// kFlagStride slot, all reset to 0 before the launch): slot 0 counts XCDs,
-// slots 1..8 count arrivals per XCD, slots 9..16 are per-XCD release words.
-// Workgroup b runs on XCD b % 8.  Barrier number n (1-based): the last
-// arrival of an XCD bumps the XCD counter, waits for every XCD, then releases
-// its own XCD by writing n.  Prior device-scope stores are complete (vmcnt 0)
-// before arriving.  Bounded waits as in exchange_point.
-constexpr int kBarrierSlots = 17;
-
-__device__ __forceinline__ bool spin_until(uint32_t* p, uint32_t target, int* err, int code, uint32_t spin_limit)
+// Overlapped per-workgroup temporal blocking (the "overlapped tiling within
+// thread blocks" that Section 2 sets the grid-barrier design against): one
+// launch per round of `steps` steps, any number of workgroups, each reading
+// its extended tile from src and writing its owned cells to dst, with no
+// synchronisation between workgroups.
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
+__global__ __launch_bounds__(WAVES * 64, 2) void k_ovl(ProbDesc P, const WgDesc* __restrict__ wgs, const T* src,
+                                                    T* dst, int steps)
 {
-    uint32_t spins = 0;
-    while (!reached(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), target)) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > spin_limit) {
-            __hip_atomic_fetch_or(err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-    }
-    return true;
-}
-
-__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err, uint32_t spin_limit)
-{
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t x = blockIdx.x % 8u;
-        const uint32_t per_xcd = (gridDim.x - x + 7u) / 8u;  // workgroups on this XCD
-        const uint32_t nxcd = gridDim.x < 8u ? gridDim.x : 8u;
-        uint32_t* xcnt = bar + (size_t)(1 + x) * kFlagStride;
-        uint32_t* xrel = bar + (size_t)(9 + x) * kFlagStride;
-        const uint32_t old = __hip_atomic_fetch_add(xcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1u == per_xcd * n) {
-            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            spin_until(bar, nxcd * n, err, 2, spin_limit);
-            __hip_atomic_store(xrel, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        spin_until(xrel, n, err, 2, spin_limit);
-    }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    const WgDesc& d = wgs[blockIdx.x];
+    char* lds = dtb_lds<T, C, R, WAVES>();
+    if (halo_varies<T, C, R, WAVES, COLMASK>(P, d))
+        run_overlapped<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true>(P, d, src, dst, steps, lds);
+    else
+        run_overlapped<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false>(P, d, src, dst, steps, lds);
 }
 
 // The tile-serial sweep (Sections 1, 3.1, 3.3, Figure 1): rounds of D steps;
@@ -1144,12 +1199,30 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
     }
 }
 
+// The register-tile instances of the batched kernel: two shapes per
+// precision (a taller and a wider one) with the same cells per lane.
+constexpr int kBatchR64a = 16, kBatchC64a = 2;  // FP64 128 x 128
+constexpr int kBatchR64b = 8, kBatchC64b = 4;   // FP64 64 x 256
+constexpr int kBatchR32a = 16, kBatchC32a = 4;  // FP32 128 x 256
+constexpr int kBatchR32b = 8, kBatchC32b = 4;   // FP32 64 x 256
+
+constexpr size_t max_sz(size_t a, size_t b) { return a > b ? a : b; }
+
+// One job with the instance the planner chose for it.
+template <typename T, int C, int R, bool FMA>
+__device__ __forceinline__ void run_job_any(const ProbDesc& P, const JobDesc& J, const WgDesc* __restrict__ table,
+                                            int local, uint32_t* flags, int* err, uint32_t spin_limit, char* lds)
+{
+    if (P.narrow_cols) run_job<T, C, R, kDtbWaves, FMA, true>(P, J, table, local, flags, err, spin_limit, lds);
+    else run_job<T, C, R, kDtbWaves, FMA, false>(P, J, table, local, flags, err, spin_limit, lds);
+}
+
 // Many grids of uneven sizes, step counts and precisions in one persistent
 // launch.  Launch slot b works through its list of (job, member) items in the
 // global job order the planner chose (so no two jobs can wait on each other).
-// FP64 runs with 2 columns x R64 rows per lane, FP32 with 4 x R32; rows
-// are always checked against the grid (small grids leave rows idle).
-template <int R64, int R32, bool FMA>
+// Each job runs with the register-tile instance the planner chose for it;
+// rows are always checked against the grid (small grids leave rows idle).
+template <bool FMA>
 __global__ __launch_bounds__(kDtbWaves * 64) void k_dtb_batched(const ProbDesc* __restrict__ probs,
                                                                 const JobDesc* __restrict__ jobs,
                                                                 const WgDesc* __restrict__ table,
@@ -1157,44 +1230,59 @@ __global__ __launch_bounds__(kDtbWaves * 64) void k_dtb_batched(const ProbDesc* 
                                                                 const WorkItem* __restrict__ wl, uint32_t* flags,
                                                                 int* err, uint32_t spin_limit)
 {
-    constexpr size_t b64 = Geo<double, 2, R64, kDtbWaves>::kLdsBytes;
-    constexpr size_t b32 = Geo<float, 4, R32, kDtbWaves>::kLdsBytes;
-    __shared__ __attribute__((aligned(16))) char lds[b64 > b32 ? b64 : b32];
+    constexpr size_t kLds = max_sz(max_sz(Geo<double, kBatchC64a, kBatchR64a, kDtbWaves>::kLdsBytes,
+                                          Geo<double, kBatchC64b, kBatchR64b, kDtbWaves>::kLdsBytes),
+                                   max_sz(Geo<float, kBatchC32a, kBatchR32a, kDtbWaves>::kLdsBytes,
+                                          Geo<float, kBatchC32b, kBatchR32b, kDtbWaves>::kLdsBytes));
+    __shared__ __attribute__((aligned(16))) char lds[kLds];
     const int slot = blockIdx.x;
     for (int i = wl_off[slot]; i < wl_off[slot + 1]; ++i) {
         const WorkItem w = wl[i];
         const JobDesc& J = jobs[w.job];
         const ProbDesc& P = probs[J.prob];
         if (P.dtype == 0) {
-            if (P.narrow_cols) run_job<double, 2, R64, kDtbWaves, FMA, true>(P, J, table, w.local, flags, err, spin_limit, lds);
-            else run_job<double, 2, R64, kDtbWaves, FMA, false>(P, J, table, w.local, flags, err, spin_limit, lds);
+            if (J.C == kBatchC64b && J.R == kBatchR64b)
+                run_job_any<double, kBatchC64b, kBatchR64b, FMA>(P, J, table, w.local, flags, err, spin_limit, lds);
+            else
+                run_job_any<double, kBatchC64a, kBatchR64a, FMA>(P, J, table, w.local, flags, err, spin_limit, lds);
         } else {
-            if (P.narrow_cols) run_job<float, 4, R32, kDtbWaves, FMA, true>(P, J, table, w.local, flags, err, spin_limit, lds);
-            else run_job<float, 4, R32, kDtbWaves, FMA, false>(P, J, table, w.local, flags, err, spin_limit, lds);
+            if (J.C == kBatchC32b && J.R == kBatchR32b)
+                run_job_any<float, kBatchC32b, kBatchR32b, FMA>(P, J, table, w.local, flags, err, spin_limit, lds);
+            else
+                run_job_any<float, kBatchC32a, kBatchR32a, FMA>(P, J, table, w.local, flags, err, spin_limit, lds);
         }
         __syncthreads();
     }
 }
 
-// The 2 x 8 kernels (resident / sweep x fma, colmask, rowcheck) of one
-// (precision, columns per lane, rows per lane, waves) instance.
-template <typename T, int C, int R, int WAVES = kDtbWaves>
-const void* pick_instance(bool sweep, bool fma, bool colmask, bool rowcheck)
+// The kernels of one (precision, columns per lane, rows per lane, waves)
+// instance: kind 0 resident (k_dtb), 1 tile-serial sweep (k_dtb_sweep), 2
+// overlapped per-workgroup blocking (k_ovl, only where OVL is set), each in 8
+// variants (fma, colmask, rowcheck); nullptr where there is none.
+template <typename T, int C, int R, int WAVES, bool OVL, bool F, bool M, bool W>
+const void* kernel_of(int kind)
 {
-#define DTB_K(F, M, W) (sweep ? (const void*)&k_dtb_sweep<T, C, R, WAVES, F, M, W> \
-                              : (const void*)&k_dtb<T, C, R, WAVES, F, M, W>)
-    const int v = (fma ? 4 : 0) | (colmask ? 2 : 0) | (rowcheck ? 1 : 0);
-    switch (v) {
-    case 0: return DTB_K(false, false, false);
-    case 1: return DTB_K(false, false, true);
-    case 2: return DTB_K(false, true, false);
-    case 3: return DTB_K(false, true, true);
-    case 4: return DTB_K(true, false, false);
-    case 5: return DTB_K(true, false, true);
-    case 6: return DTB_K(true, true, false);
-    default: return DTB_K(true, true, true);
+    if (kind == 0) return (const void*)&k_dtb<T, C, R, WAVES, F, M, W>;
+    if (kind == 1) return (const void*)&k_dtb_sweep<T, C, R, WAVES, F, M, W>;
+    if constexpr (OVL) {
+        if (kind == 2) return (const void*)&k_ovl<T, C, R, WAVES, F, M, W>;
     }
-#undef DTB_K
+    return nullptr;
+}
+
+template <typename T, int C, int R, int WAVES = kDtbWaves, bool OVL = false>
+const void* pick_instance(int kind, bool fma, bool colmask, bool rowcheck)
+{
+    switch ((fma ? 4 : 0) | (colmask ? 2 : 0) | (rowcheck ? 1 : 0)) {
+    case 0: return kernel_of<T, C, R, WAVES, OVL, false, false, false>(kind);
+    case 1: return kernel_of<T, C, R, WAVES, OVL, false, false, true>(kind);
+    case 2: return kernel_of<T, C, R, WAVES, OVL, false, true, false>(kind);
+    case 3: return kernel_of<T, C, R, WAVES, OVL, false, true, true>(kind);
+    case 4: return kernel_of<T, C, R, WAVES, OVL, true, false, false>(kind);
+    case 5: return kernel_of<T, C, R, WAVES, OVL, true, false, true>(kind);
+    case 6: return kernel_of<T, C, R, WAVES, OVL, true, true, false>(kind);
+    default: return kernel_of<T, C, R, WAVES, OVL, true, true, true>(kind);
+    }
 }
 
 }  // namespace dtb

@@ -19,12 +19,13 @@ LIB_PATH = os.path.join(HERE, "libdtb.so")
 
 F64, F32 = 0, 1
 DEBUG_TINY_SPIN, DEBUG_POISON, DEBUG_TIMING, DEBUG_DIRECT_XCHG = 1, 2, 4, 8
-PATH_AUTO, PATH_STEP, PATH_RESIDENT, PATH_SWEEP = 0, 1, 2, 3
+PATH_AUTO, PATH_STEP, PATH_RESIDENT, PATH_SWEEP, PATH_OVERLAPPED = 0, 1, 2, 3, 4
+SYNC_NEIGHBOURS, SYNC_GRID_BARRIER = 0, 1
 STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID_ARG", -2: "DTB_ERR_UNSUPPORTED", -3: "DTB_ERR_NOT_CORESIDENT",
           -4: "DTB_ERR_OUT_OF_MEMORY", -5: "DTB_ERR_HIP", -6: "DTB_ERR_TIMEOUT", -7: "DTB_ERR_NOT_PLANNED",
           -8: "DTB_ERR_MISMATCH"}
 DESCRIBE_FIELDS = ("path", "workgroups", "ghost_k", "depth_D", "ext_rows", "ext_cols", "tiles_rows",
-                   "tiles_cols", "rows_per_lane", "cols_per_lane", "big_tiles", "exact", "waves")
+                   "tiles_cols", "rows_per_lane", "cols_per_lane", "big_tiles", "exact", "waves", "sync")
 TEST_MAX_NEIGHBOURS = 24
 TEST_LAYOUT_STRIDE = 8 + TEST_MAX_NEIGHBOURS
 
@@ -43,7 +44,8 @@ class Grid(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("ghost_k", ctypes.c_int32), ("depth_D", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("max_wg", ctypes.c_int32), ("exact", ctypes.c_int32),
-                ("debug_flags", ctypes.c_int32), ("tune", ctypes.c_int32), ("waves", ctypes.c_int32)]
+                ("debug_flags", ctypes.c_int32), ("tune", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("sync", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -54,7 +56,7 @@ class Problem(ctypes.Structure):
 # Every symbol include/dtb.h and include/dtb_testing.h declare.
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
            "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep",
-           "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing")
+           "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing", "dtb_probe")
 TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
@@ -98,11 +100,14 @@ def load():
     I64P, I32P = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
     lib.dtb_test_batch.restype = ctypes.c_int32
     lib.dtb_test_batch.argtypes = [ctypes.c_int32, I64P, I64P, I32P, I64P, ctypes.c_int32, ctypes.c_int32,
-                                   ctypes.c_int32, I32P, I32P, ctypes.c_int32]
+                                   ctypes.c_int32, I32P, I32P, ctypes.c_int32, I64P]
     lib.dtb_test_sweep.restype = ctypes.c_int32
     lib.dtb_test_sweep.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    lib.dtb_probe.restype = ctypes.c_int
+    lib.dtb_probe.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
+                              ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
 
@@ -157,11 +162,11 @@ class Plan:
 
     def __init__(self, rows: int, cols: int, pitch: int, dtype: int, T_hint: int = 0, path: int = PATH_AUTO,
                  ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0, exact: bool = False,
-                 tune: bool = False, debug: int = 0, waves: int = 0):
+                 tune: bool = False, debug: int = 0, waves: int = 0, sync: int = 0):
         lib = load()
         self._h = ctypes.c_void_p()
         opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, debug, 1 if tune else 0,
-                        waves)
+                        waves, sync)
         _check(lib.dtb_plan(ctypes.byref(self._h), rows, cols, pitch, dtype, T_hint, ctypes.byref(opts)), "dtb_plan")
         self.rows, self.cols, self.pitch, self.dtype = rows, cols, pitch, dtype
 
@@ -234,6 +239,17 @@ def batch_check(stream=None):
     _check(load().dtb_batch_check(_stream(stream)), "dtb_batch_check")
 
 
+PROBE_LDS_READ, PROBE_LDS_WRITE, PROBE_COPY, PROBE_BARRIER, PROBE_FLAGS = 0, 1, 2, 3, 4
+
+
+def probe(kind: int, size: int = 0, iters: int = 1, nwg: int = 0, stream=None):
+    """dtb_probe: run one micro-benchmark; returns (milliseconds, work) -- work is bytes moved
+    (LDS, copy) or the number of barriers / exchange points."""
+    out = (ctypes.c_double * 2)()
+    _check(load().dtb_probe(int(kind), int(size), int(iters), int(nwg), _stream(stream), out), "dtb_probe")
+    return out[0], out[1]
+
+
 def cache_clear():
     load().dtb_cache_clear()
 
@@ -273,8 +289,12 @@ def test_sweep(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, wav
     return [tiles[t] for t in sorted(tiles)]
 
 
-def test_batch(shapes, r64: int = 16, r32: int = 16, n_slots: int = 256):
-    """Batch planner without a GPU.  shapes: [(rows, cols, dtype, T), ...].
+TEST_BATCH_STRIDE = 13
+
+
+def test_batch(shapes, r64: int = 0, r32: int = 0, n_slots: int = 256):
+    """Batch planner without a GPU.  shapes: [(rows, cols, dtype, T), ...].  r64 = r32 = 0: the register-tile
+    instances the batched kernel carries; else one instance per precision (FP64 2 x r64, FP32 4 x r32).
     Returns (jobs, slot_lists) or None; jobs are dicts in global order, slot_lists[s] = [(job, member), ...]."""
     n = len(shapes)
     I64 = ctypes.c_int64 * n
@@ -282,14 +302,17 @@ def test_batch(shapes, r64: int = 16, r32: int = 16, n_slots: int = 256):
     cols = I64(*[s[1] for s in shapes])
     dt = (ctypes.c_int32 * n)(*[s[2] for s in shapes])
     T = I64(*[s[3] for s in shapes])
-    jobs = (ctypes.c_int32 * (n * 10))()
+    jobs = (ctypes.c_int32 * (n * TEST_BATCH_STRIDE))()
     cap = n_slots + 1 + 2 * n * n_slots
     lists = (ctypes.c_int32 * cap)()
-    rc = load().dtb_test_batch(n, rows, cols, dt, T, r64, r32, n_slots, jobs, lists, cap)
+    info = (ctypes.c_int64 * 2)()
+    rc = load().dtb_test_batch(n, rows, cols, dt, T, r64, r32, n_slots, jobs, lists, cap, info)
     if rc < 0:
         return None
-    keys = ("prob", "g", "sweep", "ntiles", "D", "nrounds", "flag_base", "table_off", "start", "dur")
-    jl = [dict(zip(keys, jobs[j * 10:(j + 1) * 10])) for j in range(rc)]
+    test_batch.last_info = {"makespan_us": int(info[0]), "spin_limit": int(info[1])}
+    keys = ("prob", "g", "sweep", "ntiles", "D", "nrounds", "flag_base", "table_off", "start", "dur", "k", "R", "C")
+    st = TEST_BATCH_STRIDE
+    jl = [dict(zip(keys, jobs[j * st:(j + 1) * st])) for j in range(rc)]
     off = lists[:n_slots + 1]
     pairs = lists[n_slots + 1:n_slots + 1 + 2 * off[-1]]
     sl = [[(pairs[2 * i], pairs[2 * i + 1]) for i in range(off[s], off[s + 1])] for s in range(n_slots)]

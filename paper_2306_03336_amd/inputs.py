@@ -119,9 +119,13 @@ WORKLOADS = {
         _mk("j2d5pt_8192x8192_f64_T1000", 8192, 8192, 1000, "f64", "equal", 1.0, 3,
             "larger than on-chip memory: tile-serial sweep"),
         _mk("j2d5pt_3072x3072_f32_T2000", 3072, 3072, 2000, "f32", "equal", 0.0, 4,
-            "precision pair, resident"),
+            "precision pair, FP32 half: resident"),
+        _mk("j2d5pt_3072x3072_f64_T2000", 3072, 3072, 2000, "f64", "equal", 0.0, 4,
+            "precision pair, FP64 half (same input): larger than on-chip memory, tile-serial sweep"),
         _mk("j2d5pt_16384x16384_f32_T2000", 16384, 16384, 2000, "f32", "equal", 0.0, 4,
-            "precision pair, tile-serial sweep"),
+            "precision pair, FP32 half: tile-serial sweep"),
+        _mk("j2d5pt_16384x16384_f64_T2000", 16384, 16384, 2000, "f64", "equal", 0.0, 4,
+            "precision pair, FP64 half (same input): tile-serial sweep; the largest single-GPU FP64 run"),
     ]
 }
 

@@ -78,3 +78,30 @@ def test_run_rejects_bad_arguments():
     assert lib.dtb_run_plan(None, ctypes.byref(g), c, 1, None) == -1
     assert lib.dtb_plan_check(None, None) == -1
     lib.dtb_plan_destroy(None)
+
+
+def test_plan_rejects_missing_instances_before_any_hip_call():
+    """Tile instances that do not exist are DTB_ERR_UNSUPPORTED, decided on the host."""
+    cases = [(dtb.F32, dict(rows_per_lane=12)),                      # 4-column tile is FP64 only
+             (dtb.F32, dict(waves=4)),                               # half-height workgroups: FP64 only
+             (dtb.F64, dict(waves=4, rows_per_lane=16)),             # ... and 24 rows per lane only
+             (dtb.F64, dict(waves=4, path=dtb.PATH_SWEEP)),          # ... and the resident path only
+             (dtb.F64, dict(rows_per_lane=28)),                      # 28 rows: FP32 only
+             (dtb.F64, dict(rows_per_lane=10))]
+    for dtype, fields in cases:
+        o = dtb.PlanOpts()
+        for k, v in fields.items():
+            setattr(o, k, v)
+        assert _plan_rc(64, 64, 66, dtype, o) == -2, (dtype, fields)
+
+
+def test_plan_rejects_bad_sync_and_overlapped_options():
+    o = dtb.PlanOpts()
+    o.sync = 2
+    assert _plan_rc(64, 64, 66, 0, o) == -1
+    for fields in (dict(sync=1, path=dtb.PATH_SWEEP), dict(sync=1, path=dtb.PATH_OVERLAPPED),
+                   dict(path=dtb.PATH_OVERLAPPED, rows_per_lane=16), dict(path=dtb.PATH_OVERLAPPED, waves=4)):
+        o = dtb.PlanOpts()
+        for k, v in fields.items():
+            setattr(o, k, v)
+        assert _plan_rc(64, 64, 66, 0, o) == -2, fields

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from paper_2306_03336_amd import dtb, inputs
+from record import oracle_in_chunks, record
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -72,23 +73,25 @@ def test_exact_f64_bitwise(shape, R):
     coeffs = inputs.dirichlet_weights(rng)
     u_var = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols)  # halo changes along each side
     u_const = inputs.uniform_grid(rows, cols, rng, halo=0.625)                   # constant nonzero halo
-    for (k, T), u in zip([(1, 3), (2, 7), (4, 4), (5, 23), (8, 37), (16, 9), (3, 17), (8, 40)],
-                         [u_var, u_var, u_var, u_var, u_var, u_var, u_const, u_const]):
+    for i, ((k, T), u) in enumerate(zip([(1, 3), (2, 7), (4, 4), (5, 23), (8, 37), (16, 9), (3, 17), (8, 40)],
+                                        [u_var, u_var, u_var, u_var, u_var, u_var, u_const, u_const])):
         _say("exact f64", rows, cols, "R", R, "k", k, "T", T)
         try:
             got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_RESIDENT, ghost_k=k, rows_per_lane=R, exact=True)
         except dtb.DtbError as e:
             # Only the largest tiles may be unavailable: their exact variants for grids narrower than
-            # the tile spill registers, and the planner never picks a spilling kernel.
+            # the tile spill registers, and the planner never picks a spilling kernel.  The refusal
+            # depends on the shape and R only, so it comes at the first case or not at all.
             er, ec = F64_TILE[R]
-            assert e.status == -3 and R in (12, 24) and (rows < er or cols < ec), (rows, cols, R, k, e)
-            continue
+            assert i == 0 and e.status == -3 and R in (12, 24) and (rows < er or cols < ec), (rows, cols, R, k, e)
+            pytest.skip(f"exact FP64 kernel with {R} rows per lane for a {rows}x{cols} grid (narrower than its "
+                        f"{er}x{ec} tile) spills registers; the planner refuses it (DTB_ERR_NOT_CORESIDENT)")
         ref = oracle.j2d5pt_f64(u, coeffs, T)
         assert desc["path"] == dtb.PATH_RESIDENT and desc["exact"] == 1
         assert np.array_equal(got, ref), (rows, cols, R, k, T, float(np.max(np.abs(got - ref))))
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (40, 1), (2, 300), (131, 127), (256, 256), (90, 520)],
+@pytest.mark.parametrize("shape", [(1, 1), (40, 1), (2, 300), (131, 127), (256, 256), (90, 520), (517, 389)],
                          ids=lambda s: f"{s[0]}x{s[1]}")
 @pytest.mark.parametrize("R", [8, 16, 24])
 def test_exact_f32_bitwise(shape, R):
@@ -96,18 +99,47 @@ def test_exact_f32_bitwise(shape, R):
     rng = np.random.default_rng(rows * 7 + cols + R)
     coeffs = (0.05, 0.4, 0.01, 0.5, 0.04)  # strongly asymmetric: drives cells into subnormals
     u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(np.float32)
-    for k, T in [(2, 5), (6, 40), (8, 200)]:
+    for i, (k, T) in enumerate([(2, 5), (6, 40), (8, 200), (11, 60), (12, 50)]):
         _say("exact f32", rows, cols, "R", R, "k", k, "T", T)
         try:
             got, _ = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_RESIDENT, ghost_k=k,
                                rows_per_lane=R, exact=True)
         except dtb.DtbError as e:
-            # The resident FP32 kernels with 24 rows per lane spill registers, and the planner
-            # never picks a spilling kernel (the sweep instances and R = 8, 16 do not spill).
-            assert e.status == -3 and R == 24, (rows, cols, R, k, e)
-            continue
+            # The resident exact FP32 kernels with 24 rows per lane spill registers when the grid is
+            # narrower than their 192 x 256 tile (the row/column-checking variants); the planner never
+            # picks a spilling kernel.  The full-size variant does not spill and runs below.
+            assert i == 0 and e.status == -3 and R == 24 and (rows < 192 or cols < 256), (rows, cols, R, k, e)
+            pytest.skip(f"exact FP32 kernel with 24 rows per lane for a {rows}x{cols} grid (narrower than its "
+                        "192x256 tile) spills registers; the planner refuses it (DTB_ERR_NOT_CORESIDENT)")
         ref = oracle.j2d5pt_f32(u, coeffs, T)
         assert np.array_equal(got, ref), (rows, cols, R, k, T)
+
+
+@pytest.mark.parametrize("shape", [(517, 389), (700, 900), (1000, 1300)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_f32_r24_production_tile(shape):
+    """The FP32 tile the planner picks for 3072^2 (resident) and 16384^2 (swept): 24 rows x 4 columns per
+    lane at exchange depths 11 and 12.  Exact mode must equal the FP32 oracle bit for bit, resident and
+    swept; the default fused chain must equal the same chain computed with 8-row tiles bit for bit (the
+    chain per cell does not depend on the tiling), resident and swept."""
+    rows, cols = shape
+    rng = np.random.default_rng(rows + cols)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(np.float32)
+    T = 61
+    ref32 = oracle.j2d5pt_f32(u, coeffs, T)
+    fma8, d8 = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_RESIDENT, ghost_k=4, rows_per_lane=8)
+    assert d8["rows_per_lane"] == 8 and d8["exact"] == 0
+    for k in (11, 12):
+        for path, extra in ((dtb.PATH_RESIDENT, {}), (dtb.PATH_SWEEP, dict(depth_D=3 * k, max_wg=6))):
+            _say("f32 R24", rows, cols, "k", k, "path", path, "T", T)
+            got, desc = _run_plan(u, coeffs, T, dtype=np.float32, path=path, ghost_k=k, rows_per_lane=24,
+                                  exact=True, **extra)
+            assert desc["rows_per_lane"] == 24 and desc["cols_per_lane"] == 4 and desc["exact"] == 1, desc
+            assert desc["path"] == path and (path == dtb.PATH_RESIDENT or desc["big_tiles"] >= 2), desc
+            assert np.array_equal(got, ref32), ("exact", rows, cols, k, path)
+            fma, desc = _run_plan(u, coeffs, T, dtype=np.float32, path=path, ghost_k=k, rows_per_lane=24, **extra)
+            assert desc["rows_per_lane"] == 24 and desc["exact"] == 0, desc
+            assert np.array_equal(fma, fma8), ("fma", rows, cols, k, path)
 
 
 def test_exact_f32_keeps_subnormals():
@@ -248,10 +280,36 @@ def test_full_size_2048_T10000_against_oracle():
     desc = plan.describe()
     ref = oracle.j2d5pt_f64(u0, w.coeffs, w.T)
     err = oracle.rel_max_err(got, ref)
-    print(f"[result] {w.name} plan={desc} rel max err {err:.3e}")
+    record(workload=w.name, dtype="f64", plan=desc, rel_max_err_vs_fp64_oracle=err, tolerance=TOL_F64)
     assert desc["path"] == dtb.PATH_RESIDENT
     assert err <= TOL_F64
     assert np.array_equal(got[0], u0[0]) and np.array_equal(got[:, 0], u0[:, 0])
+
+
+@pytest.mark.slow
+def test_full_size_2048_three_synchronisation_designs_agree():
+    """2048^2 FP64, 10000 steps, in the three designs the benchmark compares: neighbour-flag exchange (the
+    default), a device-wide barrier at every exchange (Section 3.2 as printed) and overlapped per-workgroup
+    blocking with no synchronisation (Section 2).  The fused chain per cell does not depend on the tiling,
+    so all three give the same bits; the default is within 1e-13 of the oracle (checked above)."""
+    w = inputs.workload("j2d5pt_2048x2048_f64_T10000")
+    u0 = w.grid()
+    outs = {}
+    for label, opts in (("flags", {}), ("grid_barrier", dict(path=dtb.PATH_RESIDENT, sync=dtb.SYNC_GRID_BARRIER)),
+                        ("overlapped", dict(path=dtb.PATH_OVERLAPPED))):
+        _say("full size", w.name, label)
+        g = _dev(u0)
+        plan = dtb.plan_for(g, w.T, **opts)
+        plan.run(g, w.coeffs, w.T)
+        plan.check()
+        outs[label] = (g.cpu().numpy(), plan.describe())
+        plan.destroy()
+        del g
+    assert outs["grid_barrier"][1]["sync"] == 1 and outs["overlapped"][1]["path"] == dtb.PATH_OVERLAPPED
+    for label in ("grid_barrier", "overlapped"):
+        assert np.array_equal(outs[label][0], outs["flags"][0]), label
+    record(workload=w.name, dtype="f64", design="overlapped", plan=outs["overlapped"][1],
+           bitwise_equal_to_default_plan=True)
 
 
 def test_sine_mode_full_size_closed_form():
@@ -361,50 +419,8 @@ def test_sweep_full_size_8192_T1000():
     del g
     ref = oracle.j2d5pt_f64(u0, w.coeffs, w.T)
     err = oracle.rel_max_err(got, ref)
-    print(f"[result] {w.name} plan={desc} rel max err {err:.3e}")
+    record(workload=w.name, dtype="f64", plan=desc, rel_max_err_vs_fp64_oracle=err, tolerance=TOL_F64)
     assert err <= TOL_F64
-
-
-def test_full_size_3072_f32_T2000_against_fp64_oracle():
-    """3072^2 FP32, all 2000 steps in the default (resident) plan, against the FP64 oracle run on the
-    same float-rounded input and coefficients: the FP32 path's error, stated."""
-    w = inputs.workload("j2d5pt_3072x3072_f32_T2000")
-    u0 = w.grid().astype(np.float32)
-    _say("full size", w.name)
-    g = _dev(u0)
-    plan = dtb.plan_for(g, w.T)
-    desc = plan.describe()
-    assert desc["path"] == dtb.PATH_RESIDENT, desc
-    plan.run(g, w.coeffs, w.T)
-    plan.check()
-    got = g.cpu().numpy()
-    del g
-    ref = oracle.j2d5pt_f64(u0.astype(np.float64), np.array(w.coeffs, dtype=np.float32).astype(np.float64), w.T)
-    err = oracle.rel_max_err(got, ref)
-    print(f"[result] {w.name} plan={desc} FP32 rel max err vs FP64 oracle {err:.3e}")
-    assert err <= f32_bound(w.T)
-
-
-@pytest.mark.slow
-def test_sweep_full_size_16384_f32():
-    """16384^2 FP32 in the launch configuration planned for T=2000, run for 200 steps,
-    against the FP64 oracle on the same (float-rounded) input."""
-    w = inputs.workload("j2d5pt_16384x16384_f32_T2000")
-    u0 = w.grid().astype(np.float32)
-    _say("full size", w.name)
-    g = _dev(u0)
-    plan = dtb.plan_for(g, w.T)
-    desc = plan.describe()
-    assert desc["path"] == dtb.PATH_SWEEP, desc
-    T = 200
-    plan.run(g, w.coeffs, T)
-    plan.check()
-    got = g.cpu().numpy()
-    del g
-    ref = oracle.j2d5pt_f64(u0.astype(np.float64), np.array(w.coeffs, dtype=np.float32).astype(np.float64), T)
-    err = oracle.rel_max_err(got, ref)
-    print(f"[result] {w.name} plan={desc} T={T} FP32 rel max err vs FP64 oracle {err:.3e}")
-    assert err <= f32_bound(T)
 
 
 # ----------------------------------------------------------------------------- batched launch
@@ -527,36 +543,50 @@ def test_phase_clocks_do_not_change_results():
     plan.destroy()
 
 
+STAGED_DIRECT_CASES = [
+    ((300, 260), dict(path=dtb.PATH_RESIDENT, ghost_k=1, rows_per_lane=8)),
+    ((300, 260), dict(path=dtb.PATH_RESIDENT, ghost_k=7, rows_per_lane=8)),
+    ((517, 389), dict(path=dtb.PATH_RESIDENT, ghost_k=12)),
+    ((517, 389), dict(path=dtb.PATH_RESIDENT, ghost_k=16)),
+    ((100, 3000), dict(path=dtb.PATH_RESIDENT, ghost_k=5, max_wg=40)),
+    ((700, 650), dict(path=dtb.PATH_SWEEP, ghost_k=6, depth_D=16, max_wg=6)),
+    ((450, 900), dict(path=dtb.PATH_RESIDENT, ghost_k=9, rows_per_lane=12)),
+    ((450, 900), dict(path=dtb.PATH_RESIDENT, ghost_k=11, rows_per_lane=24, waves=4)),
+]
+
+
+def _case_id(c):
+    (rows, cols), o = c
+    return f"{rows}x{cols}-" + "-".join(f"{k}{v}" for k, v in o.items() if k != "path") + \
+        ("-sweep" if o["path"] == dtb.PATH_SWEEP else "")
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_staged_and_direct_exchange_agree(dtype):
+@pytest.mark.parametrize("case", STAGED_DIRECT_CASES, ids=_case_id)
+def test_staged_and_direct_exchange_agree(dtype, case):
     # Border strips move through the LDS staging area unless the frames are too
     # large for it; the lane-by-lane path is forced with DEBUG_DIRECT_XCHG.  Both
     # must reproduce the oracle bit for bit, tiny tiles (frames without a hole)
     # and the resident / sweep paths included.
+    (rows, cols), opts = case
     npd = np.float64 if dtype == "f64" else np.float32
     ref_fn = oracle.j2d5pt_f64 if dtype == "f64" else oracle.j2d5pt_f32
-    rng = np.random.default_rng(41)
+    if dtype == "f32" and (opts.get("waves") == 4 or opts.get("rows_per_lane") == 12):
+        # Half-height workgroups exist for FP64 with 24 rows per lane only, and 12 rows per lane (the
+        # 4-column FP64 tile) has no FP32 instance: both are refused before any HIP call.
+        with pytest.raises(dtb.DtbError) as ei:
+            dtb.Plan(rows, cols, cols + 2, dtb.F32, 0, exact=True, **opts)
+        assert ei.value.status == -2
+        return
+    rng = np.random.default_rng(41 + rows + cols)
     coeffs = inputs.dirichlet_weights(rng)
-    cases = [((300, 260), dict(path=dtb.PATH_RESIDENT, ghost_k=1, rows_per_lane=8)),
-             ((300, 260), dict(path=dtb.PATH_RESIDENT, ghost_k=7, rows_per_lane=8)),
-             ((517, 389), dict(path=dtb.PATH_RESIDENT, ghost_k=12)),
-             ((517, 389), dict(path=dtb.PATH_RESIDENT, ghost_k=16)),
-             ((100, 3000), dict(path=dtb.PATH_RESIDENT, ghost_k=5, max_wg=40)),
-             ((700, 650), dict(path=dtb.PATH_SWEEP, ghost_k=6, depth_D=16, max_wg=6)),
-             ((450, 900), dict(path=dtb.PATH_RESIDENT, ghost_k=9, rows_per_lane=12)),
-             ((450, 900), dict(path=dtb.PATH_RESIDENT, ghost_k=11, rows_per_lane=24, waves=4))]
-    for (rows, cols), opts in cases:
-        u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(npd)
-        T = 3 * opts["ghost_k"] + 2
-        ref = ref_fn(u, coeffs, T)
-        for debug in (0, dtb.DEBUG_DIRECT_XCHG):
-            _say("staged/direct", dtype, rows, cols, opts, "debug", debug, "T", T)
-            try:
-                got, _ = _run_plan(u, coeffs, T, dtype=npd, exact=True, debug=debug, **opts)
-            except dtb.DtbError as e:
-                assert e.status == -3, e  # this tiling does not fit on the chip at this precision
-                continue
-            assert np.array_equal(got, ref), (rows, cols, opts, debug)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(npd)
+    T = 3 * opts["ghost_k"] + 2
+    ref = ref_fn(u, coeffs, T)
+    for debug in (0, dtb.DEBUG_DIRECT_XCHG):
+        _say("staged/direct", dtype, rows, cols, opts, "debug", debug, "T", T)
+        got, _ = _run_plan(u, coeffs, T, dtype=npd, exact=True, debug=debug, **opts)
+        assert np.array_equal(got, ref), (rows, cols, opts, debug)
 
 
 @pytest.mark.parametrize("shape", [(150, 300), (517, 389), (2048, 700)], ids=lambda s: f"{s[0]}x{s[1]}")
@@ -572,3 +602,82 @@ def test_half_height_workgroups_bitwise(shape):
                               exact=True)
         assert desc["waves"] == 4 and desc["ext_rows"] == 96
         assert np.array_equal(got, oracle.j2d5pt_f64(u, coeffs, T)), (rows, cols, k, T)
+
+
+# ----------------------------------------------------------------------------- overlapped blocking, grid barrier
+
+@pytest.mark.parametrize("shape", [(1, 1), (45, 1), (3, 200), (127, 131), (300, 700), (517, 389), (1000, 1300)],
+                         ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("R", [8, 12, 24])
+def test_overlapped_exact_f64_bitwise(shape, R):
+    """Overlapped per-workgroup blocking (no inter-workgroup synchronisation, one launch per D steps): exact
+    mode equals the oracle bit for bit for depths from 1 to 16, odd and even round counts, varying halo."""
+    rows, cols = shape
+    rng = np.random.default_rng(rows * 31 + cols + R)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols)
+    for i, (D, T) in enumerate([(1, 3), (2, 7), (5, 23), (8, 16), (16, 37)]):
+        _say("overlapped f64", rows, cols, "R", R, "D", D, "T", T)
+        try:
+            got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_OVERLAPPED, depth_D=D, rows_per_lane=R, exact=True)
+        except dtb.DtbError as e:
+            # As for the resident kernels: exact variants narrower than their tile spill for the largest
+            # tiles, and are never chosen.
+            er, ec = F64_TILE[R]
+            assert i == 0 and e.status == -2 and R in (12, 24) and (rows < er or cols < ec), (rows, cols, R, e)
+            pytest.skip(f"exact FP64 overlapped kernel with {R} rows per lane for a {rows}x{cols} grid (narrower "
+                        f"than its {er}x{ec} tile) spills registers; the planner refuses it")
+        assert desc["path"] == dtb.PATH_OVERLAPPED and desc["depth_D"] == D and desc["rows_per_lane"] == R
+        assert np.array_equal(got, oracle.j2d5pt_f64(u, coeffs, T)), (rows, cols, R, D, T)
+
+
+@pytest.mark.parametrize("R", [8, 24])
+def test_overlapped_f32_exact_and_fma_tiling_invariant(R):
+    rows, cols, T = 700, 1100, 45
+    rng = np.random.default_rng(R)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols).astype(np.float32)
+    _say("overlapped f32", R)
+    got, _ = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_OVERLAPPED, depth_D=6, rows_per_lane=R,
+                       exact=True)
+    assert np.array_equal(got, oracle.j2d5pt_f32(u, coeffs, T))
+    fma, _ = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_OVERLAPPED, depth_D=7, rows_per_lane=R)
+    res, _ = _run_plan(u, coeffs, T, dtype=np.float32, path=dtb.PATH_RESIDENT, ghost_k=4, rows_per_lane=8)
+    assert np.array_equal(fma, res)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (127, 131), (600, 700), (1000, 1300)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_grid_barrier_sync_exact_bitwise(shape):
+    """The resident path with a device-wide barrier at every exchange point instead of neighbour flags."""
+    rows, cols = shape
+    rng = np.random.default_rng(rows + 3 * cols)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng), rng, rows, cols)
+    for k, T in [(1, 4), (3, 17), (8, 40), (11, 45)]:
+        _say("grid barrier", rows, cols, "k", k, "T", T)
+        got, desc = _run_plan(u, coeffs, T, path=dtb.PATH_RESIDENT, ghost_k=k, sync=dtb.SYNC_GRID_BARRIER,
+                              exact=True)
+        assert desc["sync"] == 1
+        assert np.array_equal(got, oracle.j2d5pt_f64(u, coeffs, T)), (rows, cols, k, T)
+    # The same plan run twice in a row (the barrier counters are reset before every launch).
+    g = _dev(u)
+    plan = dtb.plan_for(g, 0, path=dtb.PATH_RESIDENT, ghost_k=5, sync=dtb.SYNC_GRID_BARRIER, exact=True)
+    plan.run(g, coeffs, 12)
+    plan.run(g, coeffs, 19)
+    plan.check()
+    assert np.array_equal(g.cpu().numpy(), oracle.j2d5pt_f64(u, coeffs, 31))
+    plan.destroy()
+
+
+def test_probes_measure_something():
+    """The micro-benchmarks behind the measured roofline denominators run and report sane figures."""
+    ms, byt = dtb.probe(dtb.PROBE_LDS_READ, iters=256)
+    assert ms > 0 and byt > 0 and 1 < byt / (ms / 1e3) / 1e12 < 1000      # TB/s
+    ms, byt = dtb.probe(dtb.PROBE_LDS_WRITE, iters=256)
+    assert ms > 0 and 1 < byt / (ms / 1e3) / 1e12 < 1000
+    ms, byt = dtb.probe(dtb.PROBE_COPY, size=64 << 20, iters=5)
+    assert ms > 0 and 100 < byt / (ms / 1e3) / 1e9 < 100000                # GB/s
+    ms, n = dtb.probe(dtb.PROBE_BARRIER, iters=100)
+    assert n == 100 and 0.05 < ms * 1e3 / n < 1000                          # us per barrier
+    ms, n = dtb.probe(dtb.PROBE_FLAGS, iters=100)
+    assert n == 100 and 0.05 < ms * 1e3 / n < 1000

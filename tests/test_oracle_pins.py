@@ -144,3 +144,44 @@ def test_pins_reject_planted_mistake(name, tmp_path):
         except AssertionError:
             caught.append(check.__name__)
     assert caught, f"no pin rejects mutant {name}"
+
+
+# ----------------------------------------------------------------------------- the error measure itself
+
+def test_rel_max_err_known_values(oracle_mod):
+    """The relative max-norm over the interior, max|g - o| / max|o|, on hand-built arrays whose answer
+    is known: the largest |o| is a negative cell, the largest difference is negative, and the halo
+    and the pitch padding hold differences far larger than the interior's that must be ignored."""
+    rows, cols, pitch = 3, 4, 8
+    o = np.zeros((rows + 2, pitch))
+    o[1:rows + 1, 1:cols + 1] = [[0.5, -4.0, 1.0, 2.0],
+                                 [1.5, 0.25, -1.0, 3.0],
+                                 [0.0, 2.5, 1.25, -0.5]]
+    g = o.copy()
+    g[2, 3] -= 0.5            # the largest difference, negative: |d| = 0.5
+    g[3, 4] += 0.25           # a smaller one
+    g[0, :] = 1e6             # halo rows and columns: ignored
+    g[:, 0] = -1e6
+    g[:, cols + 1] = 1e6
+    g[rows + 1, :] = -1e6
+    g[:, cols + 2:] = 7e5     # pitch padding: ignored
+    # max |o| over the interior is 4.0 (a negative cell); 0.5 / 4.0 = 0.125 exactly.
+    assert oracle_mod.rel_max_err(g, o, rows, cols) == 0.125
+    # The normalisation is by the reference, not by the result: scaling g's interior changes
+    # the numerator only.
+    g2 = o.copy()
+    g2[1:rows + 1, 1:cols + 1] *= 3.0   # |d| = 2 * 4.0 = 8.0 at the -4.0 cell
+    assert oracle_mod.rel_max_err(g2, o, rows, cols) == 2.0
+    # Symmetric in the sign of the difference, zero for identical interiors.
+    assert oracle_mod.rel_max_err(o, g, rows, cols) == 0.125
+    assert oracle_mod.rel_max_err(o.copy(), o, rows, cols) == 0.0
+    # A reference whose interior is all zero: the absolute max difference.
+    z = np.zeros((rows + 2, cols + 2))
+    gz = z.copy()
+    gz[2, 2] = -3e-7
+    assert oracle_mod.rel_max_err(gz, z) == 3e-7
+    # rows/cols default to the reference's storage without padding.
+    sq = np.arange(36, dtype=np.float64).reshape(6, 6)   # interior [1:5, 1:5], max |o| = 28
+    sq2 = sq.copy()
+    sq2[4, 1] += 7.0
+    assert oracle_mod.rel_max_err(sq2, sq) == 0.25

@@ -136,8 +136,8 @@ def test_sweep_plan_properties(case):
 
 # ----------------------------------------------------------------------------- batched launch
 
-def _check_batch(shapes, n_slots=256):
-    res = dtb.test_batch(shapes, 16, 16, n_slots)
+def _check_batch(shapes, n_slots=256, r64=16, r32=16):
+    res = dtb.test_batch(shapes, r64, r32, n_slots)
     assert res is not None
     jobs, lists = res
     assert sorted(j["prob"] for j in jobs) == list(range(len(shapes)))
@@ -156,6 +156,15 @@ def _check_batch(shapes, n_slots=256):
         flags |= rng
         if j:
             assert jobs[j - 1]["start"] <= J["start"]
+    # The batch's bounded waits outlast the longest legitimate wait: a member can wait at its job's
+    # first synchronisation point for as long as the latest modelled start, and inside a job for
+    # at most the job's duration; at 27 ns per poll (one s_sleep) the limit covers 8x the makespan.
+    info = dtb.test_batch.last_info
+    makespan = max(J["start"] + J["dur"] for J in jobs)
+    assert abs(info["makespan_us"] - makespan) <= 2
+    longest_wait_us = max(J["start"] for J in jobs) + max(J["dur"] for J in jobs)
+    assert info["spin_limit"] >= 1 << 22
+    assert info["spin_limit"] * 0.027 >= min(4 * longest_wait_us, 4e9 * 0.027)
     return jobs
 
 
@@ -179,3 +188,42 @@ def test_batch_plan_mixed_sizes():
 def test_batch_plan_few_slots():
     jobs = _check_batch([(300, 300, 0, 10), (300, 300, 1, 10), (1000, 1000, 0, 20)], n_slots=4)
     assert max(j["g"] for j in jobs) <= 4
+
+
+def test_batch_spin_limit_grows_with_makespan():
+    """A batch with one long job: the wait bound follows the modelled makespan, not a fixed poll count."""
+    short = _check_batch([(300, 300, 0, 10)])
+    assert dtb.test_batch.last_info["spin_limit"] == 1 << 22
+    _check_batch([(3000, 3000, 0, 200000), (200, 200, 1, 10), (500, 500, 0, 100)])
+    info = dtb.test_batch.last_info
+    assert info["makespan_us"] > 1e5
+    assert info["spin_limit"] > 1 << 22
+    assert info["spin_limit"] * 0.027 >= 8 * info["makespan_us"] * 0.999
+    assert short
+
+
+def test_batch_autotuner_picks_per_grid():
+    """With the batched kernel's own instances (two tile shapes per precision), the planner chooses the tile
+    shape, the exchange depth and (for grids larger than the chip) the round depth per grid: the 64-grid
+    set ends up with both shapes of each precision and several k, and every choice is a candidate."""
+    from paper_2306_03336_amd import inputs
+    probs = inputs.batched_set(5)
+    shapes = [(p.side, p.side, 0 if p.dtype == "f64" else 1, p.T) for p in probs]
+    jobs = _check_batch(shapes, r64=0, r32=0)
+    insts = {0: {(16, 2), (8, 4)}, 1: {(16, 4), (8, 4)}}
+    used = {0: set(), 1: set()}
+    for J in jobs:
+        dt = shapes[J["prob"]][2]
+        assert (J["R"], J["C"]) in insts[dt]
+        used[dt].add((J["R"], J["C"]))
+        assert 1 <= J["k"] <= 16
+        if J["sweep"]:
+            assert J["D"] in (16, 24, 32, 48, 64, 96, 128) and J["ntiles"] >= 1
+    assert len({J["k"] for J in jobs}) >= 3
+    assert used[0] == insts[0], used   # both FP64 shapes are in use
+    # With slots to spare the planner takes the shortest candidate (a short, wide FP64 grid on 128 x 128
+    # tiles at k = 16: 31 workgroups); with 24 slots the 64 x 256 tile's 14 workgroups win.
+    jobs = _check_batch([(60, 3000, 0, 500), (700, 700, 0, 300)], r64=0, r32=0)
+    assert (jobs[0]["R"], jobs[0]["C"], jobs[0]["g"], jobs[0]["k"]) == (16, 2, 31, 16)
+    jobs = _check_batch([(60, 3000, 0, 500)], n_slots=24, r64=0, r32=0)
+    assert (jobs[0]["R"], jobs[0]["C"]) == (8, 4) and jobs[0]["g"] <= 24
