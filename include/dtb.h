@@ -206,6 +206,37 @@ dtb_status dtb_plan_timing(dtb_plan_t plan, uint64_t* out, int32_t n, void* stre
  */
 dtb_status dtb_plan_describe(dtb_plan_t plan, int64_t* values, int32_t n);
 
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: dtb_run for
+ * grids held on chip (the resident path, default fused chain), with no
+ * allocation of any kind.  The kernels' workspace (descriptor table, epoch
+ * flags, error word, two exchange buffers) lives in a fixed area of
+ * DTB_NOALLOC_SCRATCH_BYTES that the library reserves on every GPU it runs on
+ * and holds until the process ends; each call lays the table out there and
+ * clears the flags before its launch, and the host plans with fixed-size
+ * arrays.  Results equal dtb_run's bit for bit.
+ *
+ * grid, coeffs, T, dtype: as for dtb_run.  The grid's storage,
+ * (rows + 2) * pitch elements, must fit one exchange buffer,
+ * DTB_NOALLOC_MAX_BUFFER_BYTES (FP64: 2,359,296 elements, e.g. 1534 x 1534;
+ * FP32: twice that), else DTB_ERR_UNSUPPORTED; a grid that does not fit on
+ * chip in one wave of workgroups (at most 256, 32 per axis) gives
+ * DTB_ERR_NOT_CORESIDENT.  Both are decided before any launch; invalid
+ * arguments are rejected before any HIP call.
+ * err_flag: NULL, or a caller-owned device int32 into which the run ORs a
+ * nonzero value if one of its bounded in-kernel waits expired (the caller
+ * clears it and reads it when the stream has finished).
+ * Every call on one GPU shares that GPU's area, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads) race
+ * and must be ordered by the caller.  Three launches on `stream`: table
+ * set-up, the persistent kernel, and (with err_flag) the error report.
+ */
+#define DTB_NOALLOC_MAX_BUFFER_BYTES (18u << 20)
+#define DTB_NOALLOC_SCRATCH_BYTES (40960u + 1048576u + 256u + 2u * DTB_NOALLOC_MAX_BUFFER_BYTES)
+dtb_status dtb_run_noalloc(const dtb_grid* grid, const double coeffs[5], int64_t T, dtb_dtype dtype,
+                           int32_t* err_flag, void* stream);
+
 /* Release a plan and its workspace (after its work has completed).  NULL is a no-op. */
 void dtb_plan_destroy(dtb_plan_t plan);
 

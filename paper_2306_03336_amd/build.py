@@ -33,6 +33,7 @@ SOURCES = [(f"dtb_inst_{n}.hip", _HIP) for n in ("f32_r28", "f32_r24", "batch", 
                                                  "f64_r16", "f32_r8", "f64_r8")] + [
     ("dtb_kernels.hip", _HIP),
     ("dtb_probe.hip", _HIP),
+    ("dtb_noalloc.hip", _HIP),
     ("dtb_plan.cpp", []),
     ("dtb_api.cpp", ["-D__HIP_PLATFORM_AMD__"]),
 ]

@@ -265,6 +265,50 @@ double layout_cost_of(int nwg, int R, int C, int ER, int EC, int k, int slots_pe
     return per_cu * step + 1.5 * exch;
 }
 
+static int min_parts_fixed(int64_t lo, int64_t hi, int64_t dom, int ext, int k, int* bounds, int* ext0, bool* narrow)
+{
+    const int64_t len = hi - lo;
+    if (len < 1) return 0;
+    if (len <= ext && split_axis_core(lo, hi, dom, ext, k, 1, bounds, ext0, narrow)) return 1;
+    const int guess = first_parts_guess(len, ext, k);
+    if (guess == 0) return 0;
+    for (int64_t p = std::max(guess, 2); p <= kFixedMaxParts && p <= len; ++p)
+        if (split_axis_core(lo, hi, dom, ext, k, (int)p, bounds, ext0, narrow)) return (int)p;
+    return 0;
+}
+
+bool build_fixed_layout(int64_t rows, int64_t cols, int R, int C, int waves, int k, int n_xcd, FixedLayout* out)
+{
+    FixedLayout& L = *out;
+    L.R = R;
+    L.C = C;
+    L.waves = waves;
+    L.ER = waves * R;
+    L.EC = kWaveSize * C;
+    L.k = k;
+    if (k < 1 || rows < 1 || cols < 1) return false;
+    L.pr = min_parts_fixed(1, rows + 1, rows, L.ER, k, L.rb, L.re0, &L.narrow_rows);
+    L.pc = min_parts_fixed(1, cols + 1, cols, L.EC, k, L.cb, L.ce0, &L.narrow_cols);
+    if (L.pr < 1 || L.pc < 1 || L.pr * L.pc > kFixedMaxWg) return false;
+    L.nwg = L.pr * L.pc;
+    int scratch[kFixedMaxWg];
+    xcd_slot_order(L.pr, L.pc, interior(rows, cols), n_xcd, 0, L.slot_of_tile, scratch);
+    // Neighbours (tiles whose owned cells lie within k of a tile's) must fit a descriptor.
+    for (int a = 0; a < L.nwg; ++a) {
+        const int ar = a / L.pc, ac = a % L.pc;
+        int nnb = 0;
+        for (int b = 0; b < L.nwg; ++b) {
+            if (b == a) continue;
+            const int br = b / L.pc, bc = b % L.pc;
+            const bool meet = L.rb[br] < L.rb[ar + 1] + k && L.rb[br + 1] > L.rb[ar] - k &&
+                              L.cb[bc] < L.cb[ac + 1] + k && L.cb[bc + 1] > L.cb[ac] - k;
+            if (meet) ++nnb;
+        }
+        if (nnb > kMaxNeighbours) return false;
+    }
+    return true;
+}
+
 // Even split of [1, len + 1) into n ranges.
 static std::vector<int> even_bounds(int64_t len, int n)
 {

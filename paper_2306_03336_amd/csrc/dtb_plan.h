@@ -94,6 +94,26 @@ double exchange_time_us(int ER, int EC, int R, int C, int elem_bytes, bool stage
 double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes);
 double layout_cost_of(int nwg, int R, int C, int ER, int EC, int k, int slots_per_cu, int n_cu, int elem_bytes);
 
+// ---- resident layout without allocation (the allocation-free entry point)
+
+constexpr int kFixedMaxParts = 32;   // tiles per axis
+constexpr int kFixedMaxWg = 256;     // tiles in all
+
+// The whole interior of a rows x cols grid cut into pr x pc register tiles
+// (the layout build_layout makes for a resident grid), in fixed-size arrays.
+struct FixedLayout {
+    int R = 0, C = 0, waves = 0, ER = 0, EC = 0, k = 0;
+    int pr = 0, pc = 0, nwg = 0;
+    bool narrow_rows = false, narrow_cols = false;
+    int rb[kFixedMaxParts + 1], re0[kFixedMaxParts];  // row bounds and extended-tile origins (storage coordinates)
+    int cb[kFixedMaxParts + 1], ce0[kFixedMaxParts];  // column bounds and origins
+    int slot_of_tile[kFixedMaxWg];                     // launch slot of tile tr * pc + tc
+};
+
+// Build it; false if no layout exists within the fixed limits or a tile
+// would have more than kMaxNeighbours neighbours.  Allocates nothing.
+bool build_fixed_layout(int64_t rows, int64_t cols, int R, int C, int waves, int k, int n_xcd, FixedLayout* out);
+
 // ---- tile-serial sweep
 
 struct SweepPlan {

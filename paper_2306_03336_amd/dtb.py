@@ -56,7 +56,7 @@ class Problem(ctypes.Structure):
 # Every symbol include/dtb.h and include/dtb_testing.h declare.
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
            "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep",
-           "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing", "dtb_probe")
+           "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing", "dtb_probe", "dtb_run_noalloc")
 TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
@@ -105,6 +105,9 @@ def load():
     lib.dtb_test_sweep.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    lib.dtb_run_noalloc.restype = ctypes.c_int
+    lib.dtb_run_noalloc.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
+                                    ctypes.c_int, P, P]
     lib.dtb_probe.restype = ctypes.c_int
     lib.dtb_probe.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
                               ctypes.POINTER(ctypes.c_double)]
@@ -221,6 +224,15 @@ def run(grid, coeffs, T: int, stream=None, cols=None):
     """dtb_run: advance `grid` T steps in place with a cached default plan."""
     g = _grid(grid, cols)
     _check(load().dtb_run(ctypes.byref(g), _coeffs(coeffs), int(T), _dtype_of(grid), _stream(stream)), "dtb_run")
+
+
+def run_noalloc(grid, coeffs, T: int, err_flag=None, stream=None, cols=None):
+    """dtb_run_noalloc: as run(), with no allocation (resident grids that fit the library's fixed area).
+    err_flag: None or a one-element int32 device tensor into which a timed-out wait ORs a nonzero value."""
+    g = _grid(grid, cols)
+    errp = None if err_flag is None else ctypes.c_void_p(err_flag.data_ptr())
+    _check(load().dtb_run_noalloc(ctypes.byref(g), _coeffs(coeffs), int(T), _dtype_of(grid), errp,
+                                  _stream(stream)), "dtb_run_noalloc")
 
 
 def run_batched(problems, stream=None):

@@ -95,6 +95,26 @@ def test_plan_rejects_missing_instances_before_any_hip_call():
         assert _plan_rc(64, 64, 66, dtype, o) == -2, (dtype, fields)
 
 
+def test_noalloc_refuses_before_any_hip_call():
+    """dtb_run_noalloc: invalid arguments and grids larger than its fixed area are refused on the host."""
+    lib = dtb.load()
+    c = (ctypes.c_double * 5)(0.2, 0.2, 0.2, 0.2, 0.2)
+    assert lib.dtb_run_noalloc(None, c, 3, 0, None, None) == -1
+    g = dtb.Grid(0, 5, 5, 7)
+    assert lib.dtb_run_noalloc(ctypes.byref(g), c, 3, 0, None, None) == -1          # NULL data
+    g = dtb.Grid(0x1000, 5, 5, 6)
+    assert lib.dtb_run_noalloc(ctypes.byref(g), c, 3, 0, None, None) == -1          # pitch
+    g = dtb.Grid(0x1000, 5, 5, 7)
+    assert lib.dtb_run_noalloc(ctypes.byref(g), c, -1, 0, None, None) == -1         # T
+    assert lib.dtb_run_noalloc(ctypes.byref(g), c, 3, 7, None, None) == -1          # dtype
+    assert lib.dtb_run_noalloc(ctypes.byref(g), c, 0, 0, None, None) == 0           # T == 0: nothing to do
+    # 1534^2 FP64 (storage 1536 x 1536 = 18 MiB) is the largest square grid that fits; 1535^2 does not.
+    g = dtb.Grid(0x1000, 1535, 1535, 1537)
+    assert lib.dtb_run_noalloc(ctypes.byref(g), c, 3, 0, None, None) == -2
+    g = dtb.Grid(0x1000, 2171, 2171, 2173)                                          # FP32: 2170^2 is the largest
+    assert lib.dtb_run_noalloc(ctypes.byref(g), c, 3, 1, None, None) == -2
+
+
 def test_plan_rejects_bad_sync_and_overlapped_options():
     o = dtb.PlanOpts()
     o.sync = 2
