@@ -1,18 +1,21 @@
-"""CPU oracle for the j2d5pt iterative stencil -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for the iterative stencils -- TEST INFRASTRUCTURE ONLY.
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The GPU library never calls it and shares no code with it.
 
-``liboracle.so`` is the plain C loop in ``j2d5pt_oracle.c`` (Listing 1 of the
-paper, repeated T times as Section 3.1 and Figure 1 describe).  This module
-only loads it and marshals numpy arrays; it holds no stencil arithmetic of its
-own.  ``liboracle.so`` is compiled by ``__graft_entry__.build()`` (gcc,
+``liboracle.so`` holds the plain C loops of ``j2d5pt_oracle.c`` (Listing 1 of
+the paper, repeated T times as Section 3.1 and Figure 1 describe) and
+``j2d9pt_oracle.c`` (the 3 x 3 box, the next shape of the same method; its
+weight order and summation order are that file's stated reading).  This module
+only loads them and marshals numpy arrays; it holds no stencil arithmetic of
+its own.  ``liboracle.so`` is compiled by ``__graft_entry__.build()`` (gcc,
 ``-O2 -fopenmp -ffp-contract=off``); ``build_if_missing()`` repeats that
 command when the library is absent.
 
 Array convention (same as the C file): a 2-D array of shape
 (rows + 2, pitch), row-major, interior ``[1:rows+1, 1:cols+1]``, one-cell
-Dirichlet halo around it.  Coefficients are ordered (c, n, s, e, w).
+Dirichlet halo around it.  j2d5pt coefficients are ordered (c, n, s, e, w);
+j2d9pt coefficients (sw, s, se, w, c, e, nw, n, ne), S = row i-1, N = row i+1.
 """
 from __future__ import annotations
 
@@ -25,10 +28,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "j2d5pt_oracle.c")
+SRC9_PATH = os.path.join(_HERE, "j2d9pt_oracle.c")
 
 # The one compile line for the oracle (also used by __graft_entry__.build()).
 GCC_CMD = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-std=c11", SRC_PATH, "-o", LIB_PATH]
+           "-fno-fast-math", "-std=c11", SRC_PATH, SRC9_PATH, "-o", LIB_PATH]
 
 _lib = None
 
@@ -44,7 +48,9 @@ def _load():
         build_if_missing()
         lib = ctypes.CDLL(LIB_PATH)
         for name, ptr_t in (("oracle_j2d5pt_f64", ctypes.c_double),
-                            ("oracle_j2d5pt_f32", ctypes.c_float)):
+                            ("oracle_j2d5pt_f32", ctypes.c_float),
+                            ("oracle_j2d9pt_f64", ctypes.c_double),
+                            ("oracle_j2d9pt_f32", ctypes.c_float)):
             fn = getattr(lib, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.POINTER(ptr_t), ctypes.c_int64, ctypes.c_int64,
@@ -67,7 +73,7 @@ def _run(u: np.ndarray, rows: int, cols: int, coeffs, T: int, nthreads: int,
     if u.shape[0] != rows + 2 or u.shape[1] < cols + 2:
         raise ValueError("array shape does not hold a (rows+2) x (cols+2) grid")
     out = np.ascontiguousarray(u).copy()
-    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64).reshape(5))
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64).reshape(9 if "j2d9pt" in name else 5))
     rc = getattr(_load(), name)(out.ctypes.data_as(ctypes.POINTER(ctype)), rows, cols,
                                 out.shape[1], c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                 int(T), int(nthreads))
@@ -88,6 +94,20 @@ def j2d5pt_f32(u: np.ndarray, coeffs, T: int, nthreads: int = 0, cols: int | Non
     rows = u.shape[0] - 2
     cols = u.shape[1] - 2 if cols is None else cols
     return _run(u, rows, cols, coeffs, T, nthreads, np.float32, "oracle_j2d5pt_f32", ctypes.c_float)
+
+
+def j2d9pt_f64(u: np.ndarray, coeffs, T: int, nthreads: int = 0, cols: int | None = None) -> np.ndarray:
+    """The 3 x 3 box: u advanced T steps in FP64 (a new array; the halo, corners included, is copied unchanged)."""
+    rows = u.shape[0] - 2
+    cols = u.shape[1] - 2 if cols is None else cols
+    return _run(u, rows, cols, coeffs, T, nthreads, np.float64, "oracle_j2d9pt_f64", ctypes.c_double)
+
+
+def j2d9pt_f32(u: np.ndarray, coeffs, T: int, nthreads: int = 0, cols: int | None = None) -> np.ndarray:
+    """The 3 x 3 box with every operation in FP32 (coefficients rounded to float)."""
+    rows = u.shape[0] - 2
+    cols = u.shape[1] - 2 if cols is None else cols
+    return _run(u, rows, cols, coeffs, T, nthreads, np.float32, "oracle_j2d9pt_f32", ctypes.c_float)
 
 
 def rel_max_err(got: np.ndarray, ref: np.ndarray, rows: int | None = None, cols: int | None = None) -> float:

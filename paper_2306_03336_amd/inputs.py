@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for the j2d5pt workloads.
+"""Seeded synthetic inputs for the j2d5pt and j2d9pt workloads.
 
 This module only draws numbers and lays them out; it holds none of the
 stencil's arithmetic.  Both the GPU tests/benchmark and the CPU oracle take
@@ -8,7 +8,8 @@ Layout: a 2-D array of shape (rows + 2, pitch), row-major.  The interior is
 ``[1:rows+1, 1:cols+1]``; the one-cell ring around it is the Dirichlet halo;
 columns beyond ``cols + 1`` (pitch padding) are zero and never read.
 
-Coefficient order everywhere is (c, n, s, e, w).
+Coefficient order: j2d5pt (c, n, s, e, w); j2d9pt, the 3 x 3 box, (sw, s, se,
+w, c, e, nw, n, ne) -- rows i-1, i, i+1, each west to east.
 
 Recipes (all with ``numpy.random.default_rng``, PCG64):
 
@@ -16,6 +17,8 @@ Recipes (all with ``numpy.random.default_rng``, PCG64):
   row with ``rng.random((rows, cols))``; halo cells set to ``halo``.
 * ``dirichlet_weights(seed)``: ``rng.dirichlet(ones(5))`` -- five non-negative
   weights summing to 1 (up to the rounding of the draw), used as drawn.
+* ``box_weights(seed)``: ``rng.dirichlet(ones(9))`` -- the same for the nine
+  weights of the box.
 * ``workload(name)``: the named configurations below draw, from
   ``default_rng(seed)``, first the weights (when they are random) and then the
   interior.
@@ -33,6 +36,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 EQUAL_WEIGHTS = (0.2, 0.2, 0.2, 0.2, 0.2)
+EQUAL_WEIGHTS9 = (1.0 / 9,) * 9
 
 
 def empty_grid(rows: int, cols: int, halo: float = 0.0, pitch: int | None = None,
@@ -76,6 +80,12 @@ def dirichlet_weights(seed) -> tuple:
     return tuple(float(x) for x in w)
 
 
+def box_weights(seed) -> tuple:
+    rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)
+    w = rng.dirichlet(np.ones(9))
+    return tuple(float(x) for x in w)
+
+
 @dataclass
 class Workload:
     """One named configuration: the grid, the coefficients and the step count."""
@@ -89,6 +99,7 @@ class Workload:
     seed: int
     weights: str = "equal"   # "equal" or "dirichlet"
     note: str = ""
+    pts: int = 5             # 5: j2d5pt; 9: j2d9pt (the 3 x 3 box)
 
     @property
     def cell_updates(self) -> int:
@@ -98,16 +109,17 @@ class Workload:
         """The FP64 initial grid (draws the weights first when they are random)."""
         rng = np.random.default_rng(self.seed)
         if self.weights == "dirichlet":
-            rng.dirichlet(np.ones(5))
+            rng.dirichlet(np.ones(self.pts))
         return uniform_grid(self.rows, self.cols, rng, self.halo, pitch, dtype)
 
 
 def _mk(name, rows, cols, T, dtype, weights, halo, seed, note=""):
+    pts = 9 if name.startswith("j2d9pt") else 5
     if weights == "dirichlet":
-        coeffs = dirichlet_weights(seed)
+        coeffs = box_weights(seed) if pts == 9 else dirichlet_weights(seed)
     else:
-        coeffs = EQUAL_WEIGHTS
-    return Workload(name, rows, cols, T, dtype, coeffs, halo, seed, weights, note)
+        coeffs = EQUAL_WEIGHTS9 if pts == 9 else EQUAL_WEIGHTS
+    return Workload(name, rows, cols, T, dtype, coeffs, halo, seed, weights, note, pts)
 
 
 WORKLOADS = {
@@ -126,6 +138,14 @@ WORKLOADS = {
             "precision pair, FP32 half: tile-serial sweep"),
         _mk("j2d5pt_16384x16384_f64_T2000", 16384, 16384, 2000, "f64", "equal", 0.0, 4,
             "precision pair, FP64 half (same input): tile-serial sweep; the largest single-GPU FP64 run"),
+        _mk("j2d9pt_256x256_f64_T16", 256, 256, 16, "f64", "dirichlet", 0.25, 6,
+            "3 x 3 box, small case: every tile and a ragged edge"),
+        _mk("j2d9pt_2048x2048_f64_T10000", 2048, 2048, 10000, "f64", "dirichlet", 0.0, 7,
+            "3 x 3 box, whole grid resident on chip"),
+        _mk("j2d9pt_8192x8192_f64_T1000", 8192, 8192, 1000, "f64", "dirichlet", 1.0, 8,
+            "3 x 3 box, larger than on-chip memory: tile-serial sweep"),
+        _mk("j2d9pt_8192x8192_f32_T1000", 8192, 8192, 1000, "f32", "dirichlet", 1.0, 8,
+            "3 x 3 box, FP32 (same input as the FP64 run): tile-serial sweep"),
     ]
 }
 
