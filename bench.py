@@ -59,14 +59,14 @@ def _source_hash() -> str:
     return build.kernel_source_hash()
 
 
-def _traffic_file(workload: str) -> str:
-    return os.path.join(PROFILES, f"k_dtb_{workload[len('j2d5pt_'):]}_traffic.md")
+def _traffic_file(kernel: str, workload: str) -> str:
+    return os.path.join(PROFILES, f"{kernel}_{workload}_traffic.md")
 
 
-def _recorded_traffic(workload: str):
-    """Bytes per launch recorded for this workload, if the kernel sources still match."""
+def _recorded_traffic(kernel: str, workload: str):
+    """Bytes per launch recorded for this kernel and workload, if the kernel sources still match."""
     try:
-        text = open(_traffic_file(workload)).read()
+        text = open(_traffic_file(kernel, workload)).read()
     except OSError:
         return None
     vals = {}
@@ -460,7 +460,7 @@ def main() -> int:
     achieved = FLOPS_PER_UPDATE * updates / (avg_ms / 1e3) / 1e12
     kname = {2: "k_dtb", 3: "k_dtb_sweep"}.get(desc["path"], "k_step")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": _recorded_traffic(w.name),
+            "frac": round(achieved / peak, 4), "traffic": _recorded_traffic(kname, w.name),
             "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
             "launch_ms_min_median_max": [round(min(kern_ms), 4), round(float(np.median(kern_ms)), 4),
                                          round(max(kern_ms), 4)],

@@ -189,13 +189,16 @@ dtb_status dtb_plan_check(dtb_plan_t plan, void* stream);
 /*
  * Phase clocks of a plan made with DTB_DEBUG_TIMING, accumulated over its runs
  * since the previous call (which this call resets): waits for `stream`, then
- * fills up to `n` uint64 values, 8 per workgroup in launch order: ticks (of
+ * fills up to `n` uint64 values, 11 per workgroup in launch order: ticks (of
  * the GPU's 100 MHz real-time clock) spent in steps, publishing border strips,
  * waiting for neighbours, loading the ghost ring; number of exchanges; total
- * ticks; then, when border strips go through the LDS staging area, the ticks
- * spent moving the published strips from registers to LDS and the loaded
- * ring from the buffer to LDS (not counted in the publishing and loading
- * figures).  DTB_ERR_NOT_PLANNED if the plan has no clocks.
+ * ticks of those; then, when border strips go through the LDS staging area,
+ * the ticks spent moving the published strips from registers to LDS and the
+ * loaded ring from the buffer to LDS (not counted in the publishing and
+ * loading figures); then ticks spent loading extended tiles, storing owned
+ * cells, and (tile-serial sweep) in the device-wide barrier between big tiles
+ * (these three outside the total).  DTB_ERR_NOT_PLANNED if the plan has no
+ * clocks.
  */
 dtb_status dtb_plan_timing(dtb_plan_t plan, uint64_t* out, int32_t n, void* stream);
 

@@ -45,7 +45,7 @@ struct ProbDesc {
     int32_t narrow_cols; // 1 when some tile holds the east halo column inside it
     int32_t narrow_rows; // 1 when some tile holds the south halo row inside it
     int32_t debug;       // DTB_DEBUG_* bits (include/dtb.h)
-    double coeffs[5];    // c, n, s, e, w
+    double coeffs[9];    // j2d5pt: c, n, s, e, w; j2d9pt: sw, s, se, w, c, e, nw, n, ne
     uint64_t* timing;    // DTB_DEBUG_TIMING: kTimingSlots counters per workgroup, else null
     int32_t direct_xchg; // 1: exchange border strips lane by lane, never through the LDS staging area
     int32_t grid_sync;   // 1: a device-wide barrier at every exchange point instead of neighbour flags
@@ -55,12 +55,17 @@ struct ProbDesc {
 // Per-workgroup phase timing (s_memrealtime ticks, 100 MHz): time in steps,
 // in publishing border strips (stores and their completion), waiting for
 // neighbours' flags, loading the ghost ring, and the number of exchanges.
-constexpr int kTimingSlots = 8;
+constexpr int kTimingSlots = 11;
+constexpr int kEpochTimingSlots = 8;  // the slots kept per thread through the epoch loop (registers)
 // With the LDS staging area, publishing and loading are each split in two:
 // kTimeStageOut (registers to LDS) + kTimePublish (LDS to the buffer), and
 // kTimeStageIn (buffer to LDS) + kTimeGhost (LDS to registers).
+// kTimeLoad / kTimeStore: loading the extended tile and storing the owned
+// cells (once per segment); kTimeBarrier: the tile-serial sweep's device-wide
+// barrier between big tiles.  These three lie outside kTimeTotal.
 enum TimingSlot { kTimeSteps = 0, kTimePublish = 1, kTimeWait = 2, kTimeGhost = 3, kTimeExchanges = 4,
-                  kTimeTotal = 5, kTimeStageOut = 6, kTimeStageIn = 7 };
+                  kTimeTotal = 5, kTimeStageOut = 6, kTimeStageIn = 7, kTimeLoad = 8, kTimeStore = 9,
+                  kTimeBarrier = 10 };
 
 // One workgroup: which problem, where its register tile sits, what it owns.
 //

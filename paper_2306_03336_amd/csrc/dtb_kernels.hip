@@ -72,6 +72,81 @@ __global__ __launch_bounds__(256) void k_step(const T* __restrict__ in, T* __res
     }
 }
 
+// The same step with one 16-byte access per lane: lane l of a wave holds the V
+// = 16 / sizeof(T) consecutive columns starting at storage column
+// (64 * blockIdx.x + l) * V (2 FP64 or 4 FP32 values), for kStepRows rows plus
+// the row above and below (the column cache of Listing 1, V columns wide).
+// West/east neighbours of a lane's first and last column come from the
+// neighbouring lanes by DPP wave shifts; lanes 0 and 63 read theirs from
+// memory.  Needs rows that start 16-byte aligned (16-byte aligned base, pitch a
+// multiple of V); the launcher falls back to k_step otherwise.  Same operands,
+// same order of operations as k_step: bit for bit the same result.
+constexpr int kStepRows = 8;
+
+template <typename T>
+__device__ __forceinline__ T lane_shr1(T v)  // lane l gets lane l-1's value (lane 0: 0)
+{
+    return __builtin_amdgcn_update_dpp((T)0, v, 0x138, 0xf, 0xf, true);
+}
+template <typename T>
+__device__ __forceinline__ T lane_shl1(T v)  // lane l gets lane l+1's value (lane 63: 0)
+{
+    return __builtin_amdgcn_update_dpp((T)0, v, 0x130, 0xf, 0xf, true);
+}
+
+template <typename T, bool FMA>
+__global__ __launch_bounds__(256) void k_step_vec(const T* __restrict__ in, T* __restrict__ out, int64_t pitch,
+                                                  int rows, int cols, Coef<T> k)
+{
+    constexpr int V = 16 / (int)sizeof(T);
+    using VT = std::conditional_t<sizeof(T) == 8, double2, float4>;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int j0 = (blockIdx.x * 64 + lane) * V;  // storage column of this lane's first value
+    const int i0 = (blockIdx.y * 4 + wave) * kStepRows + 1;
+    if (i0 > rows) return;  // the whole wave
+    const bool inrow = j0 <= cols + 1;  // this lane's group lies in the row's storage (pitch is a multiple of V)
+    T c[kStepRows + 2][V];
+#pragma unroll
+    for (int q = 0; q < kStepRows + 2; ++q) {
+        const int i = i0 - 1 + q;
+        VT v{};
+        if (inrow && i <= rows + 1) v = *(const VT*)(in + (int64_t)i * pitch + j0);
+        const T* e = (const T*)&v;
+#pragma unroll
+        for (int x = 0; x < V; ++x) c[q][x] = e[x];
+    }
+#pragma unroll
+    for (int q = 0; q < kStepRows; ++q) {
+        const int i = i0 + q;
+        if (i > rows) break;  // uniform: the wave's rows
+        const T* row = in + (int64_t)i * pitch;
+        T wv = lane_shr1(c[q + 1][V - 1]);
+        T ev = lane_shl1(c[q + 1][0]);
+        if (lane == 0 && j0 >= 1 && inrow) wv = row[j0 - 1];
+        if (lane == 63 && j0 + V <= cols + 1) ev = row[j0 + V];
+        T r[V];
+#pragma unroll
+        for (int x = 0; x < V; ++x) {
+            const T W = x == 0 ? wv : c[q + 1][x - 1];
+            const T E = x == V - 1 ? ev : c[q + 1][x + 1];
+            r[x] = j2d5pt<FMA>(W, E, c[q][x], c[q + 1][x], c[q + 2][x], k);
+        }
+        T* orow = out + (int64_t)i * pitch;
+        if (j0 >= 1 && j0 + V - 1 <= cols) {
+            VT v;
+            T* e = (T*)&v;
+#pragma unroll
+            for (int x = 0; x < V; ++x) e[x] = r[x];
+            *(VT*)(orow + j0) = v;
+        } else if (inrow) {
+#pragma unroll
+            for (int x = 0; x < V; ++x)
+                if (j0 + x >= 1 && j0 + x <= cols) orow[j0 + x] = r[x];
+        }
+    }
+}
+
 // Copies the interior of src into dst (used when an odd number of one-step
 // launches leaves the result in the workspace).
 template <typename T>
@@ -115,6 +190,13 @@ static hipError_t launch_step_t(bool fma, const void* in, void* out, int64_t pit
                                 const double* coeffs, hipStream_t st)
 {
     Coef<T> k{(T)coeffs[0], (T)coeffs[1], (T)coeffs[2], (T)coeffs[3], (T)coeffs[4]};
+    constexpr int V = 16 / (int)sizeof(T);
+    if ((uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0 && pitch % V == 0) {
+        dim3 grid((unsigned)((cols + 2 + 64 * V - 1) / (64 * V)), (unsigned)((rows + 4 * kStepRows - 1) / (4 * kStepRows)));
+        if (fma) hipLaunchKernelGGL((k_step_vec<T, true>), grid, dim3(256), 0, st, (const T*)in, (T*)out, pitch, rows, cols, k);
+        else hipLaunchKernelGGL((k_step_vec<T, false>), grid, dim3(256), 0, st, (const T*)in, (T*)out, pitch, rows, cols, k);
+        return hipGetLastError();
+    }
     dim3 block(64, 4);
     dim3 grid((cols + 63) / 64, (rows + 4 * kStepIlp - 1) / (4 * kStepIlp));
     if (fma) hipLaunchKernelGGL((k_step<T, true>), grid, block, 0, st, (const T*)in, (T*)out, pitch, rows, cols, k);

@@ -47,4 +47,36 @@ __device__ __forceinline__ T j2d5pt(T W, T E, T S, T C, T N, const Coef<T>& k)
     }
 }
 
+// ---- j2d9pt: the 3 x 3 box.  Nine weights in row-major order of the block
+// -- rows i-1, i, i+1 (S to N), each west to east: (sw, s, se, w, c, e, nw, n,
+// ne) -- and the products summed in that order.  The paper presents j2d5pt as
+// a case study of the method; the box is the next shape in the same
+// framework, and this order is the library's reading.
+template <typename T>
+struct Coef9 {
+    T k[9];
+};
+
+template <typename T>
+__device__ __forceinline__ Coef9<T> load_coef9(const double* k)
+{
+    Coef9<T> c;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) c.k[q] = (T)k[q];
+    return c;
+}
+
+// a[] holds the nine neighbours in the weights' order.
+template <bool FMA, typename T>
+__device__ __forceinline__ T j2d9pt(const T (&a)[9], const Coef9<T>& w)
+{
+    T acc = w.k[0] * a[0];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+        if constexpr (FMA) acc = fma_t(w.k[q], a[q], acc);
+        else acc = acc + w.k[q] * a[q];
+    }
+    return acc;
+}
+
 }  // namespace dtb

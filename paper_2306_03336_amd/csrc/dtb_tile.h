@@ -67,6 +67,20 @@ __device__ __forceinline__ T wave_shl1(T v)
     return __builtin_amdgcn_update_dpp((T)0, v, 0x130, 0xf, 0xf, true);
 }
 
+// The same shifts without bound_ctrl: the lane without a source lane keeps
+// `old` (lane 0 for shr, lane 63 for shl) -- how the box stencil's edge lanes
+// receive the west/east halo.
+template <typename T>
+__device__ __forceinline__ T wave_shr1_or(T old, T v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
+}
+template <typename T>
+__device__ __forceinline__ T wave_shl1_or(T old, T v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
+}
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Per-lane choice without a branch: lanes whose bit is set in `mask` (a
@@ -138,9 +152,10 @@ struct Geo {
     static constexpr int EC = kWaveSize * C;
     // LDS: edge rows [parity][slot = wave + 1][top/bottom][64 * C], then per
     // extended row the west and east halo products (w*hW, e*hE) and a row of
-    // zeros (what every other lane reads on the row-by-row halo path).
+    // zeros (what every other lane reads on the row-by-row halo path) -- for
+    // the box stencil the halo values themselves, of the rows -1 .. ER.
     static constexpr int kEdgeElems = 2 * (WAVES + 2) * 2 * EC;
-    static constexpr int kHaloElems = ER * 3;
+    static constexpr int kHaloElems = (ER + 2) * 3;
     // Exchange staging area for rings up to kStageK deep (deeper rings take
     // the direct per-lane path): a block of up to 2 * kStageK full-width rows
     // (EC cells each) and a block of ER side rows (kSide left cells, then
@@ -206,9 +221,10 @@ __device__ __forceinline__ StageMap ring_map(const WgDesc& d, int kk)
     return m;
 }
 
-template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, int PTS = 5>
 struct Tile {
     using G = Geo<T, C, R, WAVES>;
+    static constexpr int kPts = PTS;  // 5: j2d5pt (Listing 1); 9: j2d9pt, the 3 x 3 box
     static constexpr int ER = G::ER;
     static constexpr int EC = G::EC;
     static constexpr int kWaves = WAVES;
@@ -229,8 +245,8 @@ struct Tile {
     int g0;          // storage row of this wave's row 0
     int col0;        // storage column of this lane's slot 0
     bool colact[C];
-    Coef<T> k;
-    T bw, be, bwe;   // halo addends when they are the same for every row
+    std::conditional_t<PTS == 9, Coef9<T>, Coef<T>> k;
+    T bw, be, bwe;   // halo addends when they are the same for every row (box: the halo values of lanes 0 / 63)
 
     __device__ __forceinline__ T* edge_row(int parity, int slot, int bottom)
     {
@@ -275,7 +291,7 @@ struct Tile {
         // (one row there costs them 1 %).
         constexpr int kHalf = R == 12 ? 2 : R / 2;
 #pragma unroll
-        for (int r = 1; r < kHalf; ++r) row<HALO_ROWS>(src, dst, r, top, bot, rows);
+        for (int r = 1; r < kHalf; ++r) any_row<HALO_ROWS>(src, dst, r, top, bot, rows);
         __syncthreads();
         const T* above = edge_row(parity, wave, 1);      // bottom row of the wave above
         const T* below = edge_row(parity, wave + 2, 0);  // top row of the wave below
@@ -286,9 +302,66 @@ struct Tile {
         }
         __builtin_amdgcn_sched_barrier(0);  // the loads issue before the rows that do not need them
 #pragma unroll
-        for (int r = kHalf; r < R - 1; ++r) row<HALO_ROWS>(src, dst, r, top, bot, rows);
-        row<HALO_ROWS>(src, dst, 0, top, bot, rows);
-        row<HALO_ROWS>(src, dst, R - 1, top, bot, rows);
+        for (int r = kHalf; r < R - 1; ++r) any_row<HALO_ROWS>(src, dst, r, top, bot, rows);
+        any_row<HALO_ROWS>(src, dst, 0, top, bot, rows);
+        any_row<HALO_ROWS>(src, dst, R - 1, top, bot, rows);
+    }
+
+    template <bool HALO_ROWS>
+    __device__ __forceinline__ void any_row(T (&src)[R][C], T (&dst)[R][C], int r, const T (&top)[C],
+                                            const T (&bot)[C], int rows)
+    {
+        if constexpr (PTS == 9) row9<HALO_ROWS>(src, dst, r, top, bot, rows);
+        else row<HALO_ROWS>(src, dst, r, top, bot, rows);
+    }
+
+    // Row r of one box-stencil step: src -> dst.  The three source rows r-1,
+    // r, r+1 (the neighbouring waves' rows top / bot at the wave's ends) and
+    // their west/east neighbours across lanes; lane 0 of a west-edge tile and
+    // lane 63 of an east-edge tile take the halo values of the three storage
+    // rows (corners included) as the shifts' fall-back.  The nine products in
+    // the weights' order (sw, s, se, w, c, e, nw, n, ne), as the oracle sums them.
+    template <bool HALO_ROWS>
+    __device__ __forceinline__ void row9(T (&src)[R][C], T (&dst)[R][C], int r, const T (&top)[C], const T (&bot)[C],
+                                         int rows)
+    {
+        if constexpr (ROWCHECK) {
+            const int g = g0 + r;
+            if (g < 1 || g > rows) return;
+        }
+        T hs = bw, hm = bw, hn = bw, es = be, em = be, en = be;
+        if constexpr (HALO_ROWS) {
+            const int q = wave * R + r;  // halo index of row offset r - 1
+            hs = hbw[q];
+            hm = hbw[q + 1];
+            hn = hbw[q + 2];
+            es = hbe[q];
+            em = hbe[q + 1];
+            en = hbe[q + 2];
+        }
+        T sr[C], mr[C], nr[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            sr[c] = (r == 0) ? top[c] : src[r - 1][c];
+            mr[c] = src[r][c];
+            nr[c] = (r == R - 1) ? bot[c] : src[r + 1][c];
+        }
+        const T sW = wave_shr1_or(hs, sr[C - 1]), sE = wave_shl1_or(es, sr[0]);
+        const T mW = wave_shr1_or(hm, mr[C - 1]), mE = wave_shl1_or(em, mr[0]);
+        const T nW = wave_shr1_or(hn, nr[C - 1]), nE = wave_shl1_or(en, nr[0]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const T a[9] = {c == 0 ? sW : sr[c - 1], sr[c], c == C - 1 ? sE : sr[c + 1],
+                            c == 0 ? mW : mr[c - 1], mr[c], c == C - 1 ? mE : mr[c + 1],
+                            c == 0 ? nW : nr[c - 1], nr[c], c == C - 1 ? nE : nr[c + 1]};
+            T v = j2d9pt<FMA>(a, k);
+            if constexpr (COLMASK) v = colact[c] ? v : dst[r][c];
+            dst[r][c] = v;
+        }
+        if constexpr (HALO_ROWS) __builtin_amdgcn_sched_barrier(0);
+        if constexpr (sizeof(T) == 4 && R > 16) {
+            if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
     }
 
     // Row r of one step: src -> dst.  top / bot are the neighbouring waves'
@@ -591,9 +664,14 @@ struct Tile {
         }
     }
 
-    // Owned cells inside the stored region -> dst.  SC1: device-scope stores
-    // (the next round of the sweep reads them on other XCDs).
-    template <bool SC1>
+    // Owned cells inside the stored region -> dst, with plain stores: the four
+    // cells of a lane in a row share 32 bytes, and plain stores of one wave
+    // meet in the L2 as whole lines (device-scope stores would each go to
+    // memory on their own, four partial writes per 32 bytes).  When the
+    // readers are other workgroups of the same launch (the tile-serial sweep),
+    // the caller makes the stores visible device-wide with an agent-scope
+    // release before it signals them (grid_barrier / group_point with
+    // release = true).
     __device__ __forceinline__ void store_owned(T (&x)[R][C], T* __restrict__ dst, int64_t pitch, const WgDesc& d)
     {
         const int r0 = max(d.own_r0, d.st_r0), r1 = min(d.own_r1, d.st_r1);
@@ -606,13 +684,7 @@ struct Tile {
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const int col = col0 + c;
-                if (col >= c0 && col < c1) {
-                    if constexpr (SC1)
-                        __hip_atomic_store(dst + (int64_t)g * pitch + col, x[r][c], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    else
-                        dst[(int64_t)g * pitch + col] = x[r][c];
-                }
+                if (col >= c0 && col < c1) dst[(int64_t)g * pitch + col] = x[r][c];
             }
         }
     }
@@ -675,11 +747,26 @@ __device__ __forceinline__ bool spin_until(uint32_t* p, uint32_t target, int* er
     return true;
 }
 
-__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err, uint32_t spin_limit)
+__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err, uint32_t spin_limit,
+                                             bool release = false, bool wait_stores = true)
 {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    // wait_stores == false: the workgroup's outstanding stores need not be
+    // complete at the barrier (the caller's memory accesses that the barrier
+    // orders -- exchange strips and flags -- have completed already), so the
+    // waves meet with a bare s_barrier and no vmcnt wait, and the stores keep
+    // draining behind it.
+    if (wait_stores) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    } else {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
     if (threadIdx.x == 0) {
+        // release: the workgroup's plain stores (all complete in this XCD's L2
+        // by now) are written back so that every XCD sees them after the barrier.
+        if (release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const uint32_t x = blockIdx.x % 8u;
         const uint32_t per_xcd = (gridDim.x - x + 7u) / 8u;  // workgroups on this XCD
         const uint32_t nxcd = gridDim.x < 8u ? gridDim.x : 8u;
@@ -693,8 +780,14 @@ __device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err
         }
         spin_until(xrel, n, err, 2, spin_limit);
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    if (wait_stores) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    } else {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
 }
 
 // The synchronisation at an exchange point: by default each workgroup waits
@@ -737,7 +830,7 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
     const bool staged = kStagedHere && !P.direct_xchg && kk <= Tile_::G::kStageK;
     // DTB_DEBUG_TIMING: phase clocks of thread 0 (uniform branch, off by default).
     const bool timing = P.timing != nullptr;
-    uint64_t tm[kTimingSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t tm[kEpochTimingSlots] = {};  // the slots below kTimeLoad (the others are added directly)
     uint64_t t0 = timing ? __builtin_amdgcn_s_memrealtime() : 0, t_start = t0;
     while (done < steps) {
         const int64_t left = steps - done;
@@ -844,7 +937,7 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
         tm[kTimeTotal] += t1 - t_start;
         if (threadIdx.x == 0) {
             uint64_t* out = P.timing + (size_t)me * kTimingSlots;
-            for (int i = 0; i < kTimingSlots; ++i) atomicAdd((unsigned long long*)(out + i), (unsigned long long)tm[i]);
+            for (int i = 0; i < kEpochTimingSlots; ++i) atomicAdd((unsigned long long*)(out + i), (unsigned long long)tm[i]);
         }
     }
     // Neighbours read their initial ghost ring from the source grid; when the
@@ -853,6 +946,17 @@ __device__ __forceinline__ void run_epochs(Tl& t, const ProbDesc& P, const WgDes
         ++epoch;
         sync_point(P, flags, me, d, base, epoch, err, spin_limit);
     }
+}
+
+// DTB_DEBUG_TIMING: wait for this workgroup's memory accesses, then add the
+// ticks since t0 to its clock `slot`.
+__device__ __forceinline__ void add_clock(const ProbDesc& P, int me, int slot, uint64_t t0)
+{
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __syncthreads();
+    const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+    if (threadIdx.x == 0)
+        atomicAdd((unsigned long long*)(P.timing + (size_t)me * kTimingSlots + slot), (unsigned long long)(t1 - t0));
 }
 
 // Load a workgroup's extended tile from src into both register sets, the
@@ -877,7 +981,8 @@ __device__ __forceinline__ void load_tile(Tl& t, const ProbDesc& P, const WgDesc
     t.lane = threadIdx.x & 63;
     t.g0 = d.ext_r0 + t.wave * R;
     t.col0 = d.ext_c0 + t.lane * C;
-    t.k = load_coef<T>(P.coeffs);
+    if constexpr (Tl::kPts == 9) t.k = load_coef9<T>(P.coeffs);
+    else t.k = load_coef<T>(P.coeffs);
 #pragma unroll
     for (int c = 0; c < C; ++c) t.colact[c] = (t.col0 + c) <= cols;
 
@@ -917,24 +1022,45 @@ __device__ __forceinline__ void load_tile(Tl& t, const ProbDesc& P, const WgDesc
     // the outermost ghost columns of an interior tile are expendable).
     const bool west_edge = d.ext_c0 == 1;
     const bool east_edge = !COLMASK && d.ext_c0 + G::EC - 1 == cols;
-    for (int idx = threadIdx.x; idx < G::ER; idx += WAVES * kWaveSize) {
-        const int g = d.ext_r0 + idx;
-        const bool grow = g >= 1 && g <= rows;
-        hx[idx] = (west_edge && grow) ? t.k.w * grid[(int64_t)g * pitch] : T(0);
-        hx[G::ER + idx] = (east_edge && grow) ? t.k.e * grid[(int64_t)g * pitch + cols + 1] : T(0);
-        hx[2 * G::ER + idx] = T(0);
-    }
-    __syncthreads();
-
-    // With HALO_ROWS == false the products are the same on every row (checked
-    // by the caller) and live in registers.
     const T zero = T(0);
-    t.bw = t.lane == 0 ? hx[0] : zero;
-    t.be = t.lane == 63 ? hx[G::ER] : zero;
-    t.bwe = t.lane == 0 ? hx[0] : (t.lane == 63 ? hx[G::ER] : zero);
-    t.hbw = hx + (t.lane == 0 ? 0 : 2 * G::ER);
-    t.hbe = hx + (t.lane == 63 ? G::ER : 2 * G::ER);
-    t.hbwe = hx + (t.lane == 0 ? 0 : (t.lane == 63 ? G::ER : 2 * G::ER));
+    if constexpr (Tl::kPts == 9) {
+        // Box: the halo values themselves, of the storage rows ext_r0 - 1 ..
+        // ext_r0 + ER (the rows the tile's diagonal neighbours reach, corner
+        // cells included): [0, ER+2) west, [ER+2, 2ER+4) east, then zeros.
+        constexpr int H = G::ER + 2;
+        for (int idx = threadIdx.x; idx < H; idx += WAVES * kWaveSize) {
+            const int g = d.ext_r0 - 1 + idx;
+            const bool grow = g >= 0 && g <= rows + 1;
+            hx[idx] = (west_edge && grow) ? grid[(int64_t)g * pitch] : T(0);
+            hx[H + idx] = (east_edge && grow) ? grid[(int64_t)g * pitch + cols + 1] : T(0);
+            hx[2 * H + idx] = T(0);
+        }
+        __syncthreads();
+        t.bw = t.lane == 0 ? hx[1] : zero;
+        t.be = t.lane == 63 ? hx[H + 1] : zero;
+        t.bwe = zero;
+        t.hbw = hx + (t.lane == 0 ? 0 : 2 * H);
+        t.hbe = hx + (t.lane == 63 ? H : 2 * H);
+        t.hbwe = hx + 2 * H;
+    } else {
+        for (int idx = threadIdx.x; idx < G::ER; idx += WAVES * kWaveSize) {
+            const int g = d.ext_r0 + idx;
+            const bool grow = g >= 1 && g <= rows;
+            hx[idx] = (west_edge && grow) ? t.k.w * grid[(int64_t)g * pitch] : T(0);
+            hx[G::ER + idx] = (east_edge && grow) ? t.k.e * grid[(int64_t)g * pitch + cols + 1] : T(0);
+            hx[2 * G::ER + idx] = T(0);
+        }
+        __syncthreads();
+
+        // With HALO_ROWS == false the products are the same on every row (checked
+        // by the caller) and live in registers.
+        t.bw = t.lane == 0 ? hx[0] : zero;
+        t.be = t.lane == 63 ? hx[G::ER] : zero;
+        t.bwe = t.lane == 0 ? hx[0] : (t.lane == 63 ? hx[G::ER] : zero);
+        t.hbw = hx + (t.lane == 0 ? 0 : 2 * G::ER);
+        t.hbe = hx + (t.lane == 63 ? G::ER : 2 * G::ER);
+        t.hbwe = hx + (t.lane == 0 ? 0 : (t.lane == 63 ? G::ER : 2 * G::ER));
+    }
 }
 
 // One segment of work for one workgroup: load its extended tile from src,
@@ -943,16 +1069,21 @@ __device__ __forceinline__ void load_tile(Tl& t, const ProbDesc& P, const WgDesc
 // and written with device-scope accesses (other XCDs wrote / will read them
 // inside the same launch).
 template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS, bool SWEEP,
-          bool STAGED = true>
+          bool STAGED = true, int PTS = 5>
 __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int64_t steps,
                                             int me, uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
                                             uint32_t spin_limit, char* lds)
 {
-    using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK>;
+    using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, PTS>;
     Tl t;
+    const bool timing = P.timing != nullptr;  // DTB_DEBUG_TIMING (uniform branch)
+    uint64_t t0 = timing ? __builtin_amdgcn_s_memrealtime() : 0;
     load_tile<SWEEP>(t, P, d, src, lds);
+    if (timing) add_clock(P, me, kTimeLoad, t0);
     run_epochs<HALO_ROWS, STAGED>(t, P, d, steps, me, flags, base, epoch, err, spin_limit);
-    t.template store_owned<SWEEP>(t.a, dst, P.pitch, d);
+    if (timing) t0 = __builtin_amdgcn_s_memrealtime();
+    t.store_owned(t.a, dst, P.pitch, d);
+    if (timing) add_clock(P, me, kTimeStore, t0);
 }
 
 // Overlapped (trapezoidal) temporal blocking of one workgroup, with no
@@ -979,12 +1110,14 @@ __device__ __forceinline__ void run_overlapped(const ProbDesc& P, const WgDesc& 
 #pragma unroll
             for (int c = 0; c < C; ++c) t.a[r][c] = t.b[r][c];
     }
-    t.template store_owned<false>(t.a, dst, P.pitch, d);
+    t.store_owned(t.a, dst, P.pitch, d);
 }
 
 // Does the west or east halo of this tile's rows change from row to row?
-// (Only edge tiles look: an interior tile never reads the halo.)
-template <typename T, int C, int R, int WAVES, bool COLMASK>
+// (Only edge tiles look: an interior tile never reads the halo.)  The box
+// stencil also reads the halo of the rows just above and below the tile
+// (corner cells included).
+template <typename T, int C, int R, int WAVES, bool COLMASK, int PTS = 5>
 __device__ __forceinline__ bool halo_varies(const ProbDesc& P, const WgDesc& d)
 {
     using G = Geo<T, C, R, WAVES>;
@@ -994,7 +1127,8 @@ __device__ __forceinline__ bool halo_varies(const ProbDesc& P, const WgDesc& d)
     const bool east_edge = !COLMASK && d.ext_c0 + G::EC - 1 == cols;
     bool mine = false;
     if (west_edge || east_edge) {
-        const int r0 = max(d.ext_r0, 1), r1 = min(d.ext_r0 + G::ER - 1, rows);
+        const int r0 = PTS == 9 ? max(d.ext_r0 - 1, 0) : max(d.ext_r0, 1);
+        const int r1 = PTS == 9 ? min(d.ext_r0 + G::ER, rows + 1) : min(d.ext_r0 + G::ER - 1, rows);
         const T w0 = grid[(int64_t)r0 * P.pitch], e0 = grid[(int64_t)r0 * P.pitch + cols + 1];
         for (int g = r0 + (int)threadIdx.x; g <= r1; g += WAVES * kWaveSize) {
             if (west_edge && grid[(int64_t)g * P.pitch] != w0) mine = true;
@@ -1012,7 +1146,7 @@ __device__ __forceinline__ char* dtb_lds()
     return lds;
 }
 
-template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, int PTS = 5>
 __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb(ProbDesc P, const WgDesc* __restrict__ wgs,
                                                     uint32_t* flags, int* err, uint32_t spin_limit)
 {
@@ -1022,12 +1156,12 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb(ProbDesc P, const WgDesc*
     const uint32_t base = __hip_atomic_load(flags + (size_t)me * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t epoch = 0;
     T* grid = (T*)P.grid;
-    if (halo_varies<T, C, R, WAVES, COLMASK>(P, d))
-        run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false>(P, d, grid, grid, P.T, me, flags, base,
-                                                                          epoch, err, spin_limit, lds);
+    if (halo_varies<T, C, R, WAVES, COLMASK, PTS>(P, d))
+        run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false, true, PTS>(P, d, grid, grid, P.T, me, flags,
+                                                                                    base, epoch, err, spin_limit, lds);
     else
-        run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false>(P, d, grid, grid, P.T, me, flags, base,
-                                                                           epoch, err, spin_limit, lds);
+        run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false, true, PTS>(P, d, grid, grid, P.T, me, flags,
+                                                                                     base, epoch, err, spin_limit, lds);
 }
 
 // Overlapped per-workgroup temporal blocking (the "overlapped tiling within
@@ -1052,7 +1186,7 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_ovl(ProbDesc P, const WgDesc*
 // reading its computed region (valid part + D ring) from buffer A and writing
 // its valid part to buffer B; a device-wide barrier separates tiles.  Round r
 // reads bufs[r & 1] and writes bufs[(r + 1) & 1]; bufs[0] is the grid.
-template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK>
+template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, int PTS = 5>
 __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepArgs S, const WgDesc* __restrict__ table,
                                                           uint32_t* flags, int* err, uint32_t spin_limit)
 {
@@ -1062,6 +1196,13 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepAr
     uint32_t epoch = 0;
     uint32_t nbar = 0;
     int64_t done = 0;
+    // Within a round the big tiles are independent (each reads A and writes its
+    // own valid part of B), so the barrier between two of them only keeps the
+    // next tile's exchanges from overwriting strips of this one that a slower
+    // workgroup may still read: it does not wait for this tile's stores to B,
+    // which drain while the next tile loads.  B is read in the next round only:
+    // the round's last barrier waits for the stores and makes them visible to
+    // every XCD (agent-scope release).
     for (int round = 0; round < S.nrounds; ++round) {
         const T* A = (const T*)S.bufs[round & 1];
         T* B = (T*)S.bufs[(round + 1) & 1];
@@ -1073,15 +1214,18 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepAr
                 // Idle for this tile: keep the epoch count in step with the others.
                 const int64_t per = (steps + P.k - 1) / P.k - 1;
                 epoch += per > 0 ? (uint32_t)per : 1u;
-            } else if (halo_varies<T, C, R, WAVES, COLMASK>(P, d)) {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, true>(P, d, A, B, steps, me, flags, base,
-                                                                                 epoch, err, spin_limit, lds);
+            } else if (halo_varies<T, C, R, WAVES, COLMASK, PTS>(P, d)) {
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, true, true, PTS>(P, d, A, B, steps, me, flags,
+                                                                                           base, epoch, err, spin_limit, lds);
             } else {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, true>(P, d, A, B, steps, me, flags, base,
-                                                                                  epoch, err, spin_limit, lds);
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, true, true, PTS>(P, d, A, B, steps, me, flags,
+                                                                                            base, epoch, err, spin_limit, lds);
             }
             ++nbar;
-            grid_barrier(S.bar, nbar, err, spin_limit);
+            const bool end_of_round = tile + 1 == S.ntiles;
+            const uint64_t tb = P.timing ? __builtin_amdgcn_s_memrealtime() : 0;
+            grid_barrier(S.bar, nbar, err, spin_limit, end_of_round, end_of_round);
+            if (P.timing) add_clock(P, me, kTimeBarrier, tb);
         }
         done += steps;
     }
@@ -1099,10 +1243,11 @@ constexpr int kDtbWaves = 8;
 // Group-wide synchronisation point of a batched job: raise this member's
 // flag, wait (bounded) until every member's flag reached `target`.
 __device__ __forceinline__ void group_point(uint32_t* flags, int flag_base, int g, int local, uint32_t target,
-                                            int* err, uint32_t spin_limit)
+                                            int* err, uint32_t spin_limit, bool release = false)
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+    if (threadIdx.x == 0 && release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // as in grid_barrier
     if (threadIdx.x == 0)
         __hip_atomic_store(flags + (size_t)(flag_base + local) * kFlagStride, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = threadIdx.x; i < g; i += blockDim.x) {
@@ -1182,7 +1327,7 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
                                                                               epoch, err, spin_limit, lds);
             }
             ++epoch;
-            group_point(flags, J.flag_base, J.g, local, base + epoch, err, spin_limit);
+            group_point(flags, J.flag_base, J.g, local, base + epoch, err, spin_limit, true);
         }
         done += steps;
     }
@@ -1255,33 +1400,33 @@ __global__ __launch_bounds__(kDtbWaves * 64) void k_dtb_batched(const ProbDesc* 
     }
 }
 
-// The kernels of one (precision, columns per lane, rows per lane, waves)
-// instance: kind 0 resident (k_dtb), 1 tile-serial sweep (k_dtb_sweep), 2
-// overlapped per-workgroup blocking (k_ovl, only where OVL is set), each in 8
-// variants (fma, colmask, rowcheck); nullptr where there is none.
-template <typename T, int C, int R, int WAVES, bool OVL, bool F, bool M, bool W>
+// The kernels of one (precision, columns per lane, rows per lane, waves,
+// stencil) instance: kind 0 resident (k_dtb), 1 tile-serial sweep
+// (k_dtb_sweep), 2 overlapped per-workgroup blocking (k_ovl, only where OVL is
+// set), each in 8 variants (fma, colmask, rowcheck); nullptr where there is none.
+template <typename T, int C, int R, int WAVES, bool OVL, bool F, bool M, bool W, int PTS>
 const void* kernel_of(int kind)
 {
-    if (kind == 0) return (const void*)&k_dtb<T, C, R, WAVES, F, M, W>;
-    if (kind == 1) return (const void*)&k_dtb_sweep<T, C, R, WAVES, F, M, W>;
+    if (kind == 0) return (const void*)&k_dtb<T, C, R, WAVES, F, M, W, PTS>;
+    if (kind == 1) return (const void*)&k_dtb_sweep<T, C, R, WAVES, F, M, W, PTS>;
     if constexpr (OVL) {
         if (kind == 2) return (const void*)&k_ovl<T, C, R, WAVES, F, M, W>;
     }
     return nullptr;
 }
 
-template <typename T, int C, int R, int WAVES = kDtbWaves, bool OVL = false>
+template <typename T, int C, int R, int WAVES = kDtbWaves, bool OVL = false, int PTS = 5>
 const void* pick_instance(int kind, bool fma, bool colmask, bool rowcheck)
 {
     switch ((fma ? 4 : 0) | (colmask ? 2 : 0) | (rowcheck ? 1 : 0)) {
-    case 0: return kernel_of<T, C, R, WAVES, OVL, false, false, false>(kind);
-    case 1: return kernel_of<T, C, R, WAVES, OVL, false, false, true>(kind);
-    case 2: return kernel_of<T, C, R, WAVES, OVL, false, true, false>(kind);
-    case 3: return kernel_of<T, C, R, WAVES, OVL, false, true, true>(kind);
-    case 4: return kernel_of<T, C, R, WAVES, OVL, true, false, false>(kind);
-    case 5: return kernel_of<T, C, R, WAVES, OVL, true, false, true>(kind);
-    case 6: return kernel_of<T, C, R, WAVES, OVL, true, true, false>(kind);
-    default: return kernel_of<T, C, R, WAVES, OVL, true, true, true>(kind);
+    case 0: return kernel_of<T, C, R, WAVES, OVL, false, false, false, PTS>(kind);
+    case 1: return kernel_of<T, C, R, WAVES, OVL, false, false, true, PTS>(kind);
+    case 2: return kernel_of<T, C, R, WAVES, OVL, false, true, false, PTS>(kind);
+    case 3: return kernel_of<T, C, R, WAVES, OVL, false, true, true, PTS>(kind);
+    case 4: return kernel_of<T, C, R, WAVES, OVL, true, false, false, PTS>(kind);
+    case 5: return kernel_of<T, C, R, WAVES, OVL, true, false, true, PTS>(kind);
+    case 6: return kernel_of<T, C, R, WAVES, OVL, true, true, false, PTS>(kind);
+    default: return kernel_of<T, C, R, WAVES, OVL, true, true, true, PTS>(kind);
     }
 }
 

@@ -27,6 +27,7 @@ STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID_ARG", -2: "DTB_ERR_UNSUPPORTED", -3:
 DESCRIBE_FIELDS = ("path", "workgroups", "ghost_k", "depth_D", "ext_rows", "ext_cols", "tiles_rows",
                    "tiles_cols", "rows_per_lane", "cols_per_lane", "big_tiles", "exact", "waves", "sync")
 TEST_MAX_NEIGHBOURS = 24
+TIMING_SLOTS = 11
 TEST_LAYOUT_STRIDE = 8 + TEST_MAX_NEIGHBOURS
 
 
@@ -184,17 +185,21 @@ class Plan:
     def timing(self, stream=None):
         """Per-workgroup phase clocks (DTB_DEBUG_TIMING plans): list of dicts, times in microseconds."""
         n = self.describe()["workgroups"]
-        buf = (ctypes.c_uint64 * (8 * n))()
-        _check(load().dtb_plan_timing(self._h, buf, 8 * n, _stream(stream)), "dtb_plan_timing")
+        m = TIMING_SLOTS
+        buf = (ctypes.c_uint64 * (m * n))()
+        _check(load().dtb_plan_timing(self._h, buf, m * n, _stream(stream)), "dtb_plan_timing")
         names = ("steps", "publish", "wait", "ghost")
         out = []
         for i in range(n):
-            v = buf[8 * i:8 * i + 8]
+            v = buf[m * i:m * i + m]
             d = {k: v[j] / 100.0 for j, k in enumerate(names)}  # 100 MHz ticks -> us
             d["exchanges"] = int(v[4])
             d["total"] = v[5] / 100.0
             d["stage_out"] = v[6] / 100.0
             d["stage_in"] = v[7] / 100.0
+            d["load"] = v[8] / 100.0
+            d["store"] = v[9] / 100.0
+            d["barrier"] = v[10] / 100.0
             out.append(d)
         return out
 

@@ -178,6 +178,28 @@ def test_step_path_bitwise_and_matches_dtb_fma(shape):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape_pitch", [(1, 1, 4), (64, 1, 4), (33, 130, 132), (129, 254, 256), (129, 255, 260),
+                                         (200, 510, 513), (77, 2046, 2048)],
+                         ids=lambda s: f"{s[0]}x{s[1]}p{s[2]}")
+def test_step_kernel_both_access_widths_bitwise(dtype, shape_pitch):
+    """The one-step baseline uses one 16-byte access per lane when rows start 16-byte aligned (pitch a
+    multiple of 2 FP64 / 4 FP32 values) and one 8- or 4-byte access otherwise; exact mode equals the oracle
+    bit for bit either way, pitch padding untouched."""
+    rows, cols, pitch = shape_pitch
+    npd = np.float64 if dtype == "f64" else np.float32
+    rng = np.random.default_rng(rows + cols + pitch)
+    coeffs = inputs.dirichlet_weights(rng)
+    u = _random_halo(inputs.uniform_grid(rows, cols, rng, pitch=pitch), rng, rows, cols).astype(npd)
+    u[:, cols + 2:] = -9.0
+    ref_fn = oracle.j2d5pt_f64 if dtype == "f64" else oracle.j2d5pt_f32
+    for T in (1, 2, 5):
+        _say("step kernel", dtype, rows, cols, pitch, "T", T)
+        got, desc = _run_plan(u, coeffs, T, dtype=npd, cols=cols, path=dtb.PATH_STEP, exact=True)
+        assert np.array_equal(got, ref_fn(u, coeffs, T, cols=cols)), (rows, cols, pitch, T)
+        assert np.array_equal(got[:, cols + 2:], u[:, cols + 2:])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_fma_default_within_tolerance(dtype):
     rows, cols, T = 600, 700, 300
     coeffs = inputs.dirichlet_weights(17)
