@@ -43,7 +43,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X FP64 vector (FMA counted as 2 flops)
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # with packed FP32; the kernels are built without it (78.6 unpacked)
 PEAK_HBM_GBS = 8000.0
 PEAK_LDS_TBS = 256 * 2.4e9 * 128 / 1e12  # datasheet LDS rate, 128 B per clock per CU
-FLOPS_PER_UPDATE = 9
+FLOPS_PER_UPDATE = 9      # j2d5pt: five products, four additions
+FLOPS_PER_UPDATE9 = 17    # the 3 x 3 box: nine products, eight additions
 HEADLINE = "j2d5pt_16384x16384_f64_T2000"
 
 # HBM traffic per launch of the headline kernel (rocprofv3 --pmc FETCH_SIZE and
@@ -131,10 +132,10 @@ def _time_runs(run, torch, stream, reps):
     return [e0.elapsed_time(e1) for e0, e1 in ev]
 
 
-def _step_baseline(dtb, torch, stream, g, u0, coeffs, T, reps):
-    """The untiled kernel: T launches of k_step, timed as launches (once) and as a HIP graph of the T
-    launches (reps replays); the faster is the baseline."""
-    sp = dtb.plan_for(g, T, path=dtb.PATH_STEP)
+def _step_baseline(dtb, torch, stream, g, u0, coeffs, T, reps, stencil=5):
+    """The untiled kernel: T launches of the one-step kernel, timed as launches (once) and as a HIP graph of
+    the T launches (reps replays); the faster is the baseline."""
+    sp = dtb.plan_for(g, T, path=dtb.PATH_STEP, stencil=stencil)
     g.copy_(u0)
     sp.run(g, coeffs, min(T, 200))
     torch.cuda.synchronize()
@@ -193,10 +194,10 @@ def _denominators(dtb):
     return out
 
 
-def _rooflines(gc, dtype, desc, T, updates, dtb_ms, den):
+def _rooflines(gc, dtype, desc, T, updates, dtb_ms, den, flops=FLOPS_PER_UPDATE):
     b = 8 if dtype == "f64" else 4
     peak = PEAK_FP64_VECTOR_TFLOPS if dtype == "f64" else PEAK_FP32_VECTOR_TFLOPS
-    tflops = FLOPS_PER_UPDATE * gc / 1e3
+    tflops = flops * gc / 1e3
     r = {"valu_TFLOPs": round(tflops, 3), "valu_peak_TFLOPs": peak, "frac_of_valu_peak": round(tflops / peak, 4),
          "frac_of_untiled_hbm_roofline": round(gc / (PEAK_HBM_GBS / (2 * b)), 3)}
     if desc is not None and desc.get("path") in (2, 3):
@@ -216,7 +217,7 @@ def _one_config(dtb, inputs, torch, np, stream, name, records, den, reps=5):
     dt = torch.float64 if w.dtype == "f64" else torch.float32
     u0 = torch.from_numpy(w.grid()).to(device="cuda", dtype=dt)
     g = u0.clone()
-    plan = dtb.plan_for(g, w.T)
+    plan = dtb.plan_for(g, w.T, stencil=w.pts)
     plan.run(g, w.coeffs, w.T)       # warm-up
     plan.check()
     g.copy_(u0)
@@ -224,7 +225,7 @@ def _one_config(dtb, inputs, torch, np, stream, name, records, den, reps=5):
     plan.check()
     d = plan.describe()
     plan.destroy()
-    launches, graph_ms = _step_baseline(dtb, torch, stream, g, u0, w.coeffs, w.T, reps)
+    launches, graph_ms = _step_baseline(dtb, torch, stream, g, u0, w.coeffs, w.T, reps, w.pts)
     del g, u0
     torch.cuda.empty_cache()
     updates = w.cell_updates
@@ -247,7 +248,8 @@ def _one_config(dtb, inputs, torch, np, stream, name, records, den, reps=5):
         base["copy_reference"] = copy_key
     return {"workload": name, "dtype": w.dtype, "T": w.T, "cell_updates": updates, "plan": d, "dtb": st,
             "step_kernel": base, "dtb_speedup": round(base["median_ms"] / st["median_ms"], 3),
-            "roofline": _rooflines(st["GCells_per_s"], w.dtype, d, w.T, updates, st["median_ms"], den),
+            "roofline": _rooflines(st["GCells_per_s"], w.dtype, d, w.T, updates, st["median_ms"], den,
+                                   FLOPS_PER_UPDATE9 if w.pts == 9 else FLOPS_PER_UPDATE),
             "error_vs_oracle": _error_for(records, name, w.dtype)}
 
 
@@ -315,7 +317,10 @@ SECONDARY = [("cfg1_256_f64", "j2d5pt_256x256_f64_T16", 100),
              ("cfg3_8192_f64_sweep", "j2d5pt_8192x8192_f64_T1000", 5),
              ("cfg4a_3072_f32_resident", "j2d5pt_3072x3072_f32_T2000", 5),
              ("cfg4a_3072_f64_sweep", "j2d5pt_3072x3072_f64_T2000", 5),
-             ("cfg4b_16384_f32_sweep", "j2d5pt_16384x16384_f32_T2000", 5)]
+             ("cfg4b_16384_f32_sweep", "j2d5pt_16384x16384_f32_T2000", 5),
+             ("cfg6_box_2048_f64_resident", "j2d9pt_2048x2048_f64_T10000", 5),
+             ("cfg7_box_8192_f64_sweep", "j2d9pt_8192x8192_f64_T1000", 5),
+             ("cfg7_box_8192_f32_sweep", "j2d9pt_8192x8192_f32_T1000", 5)]
 
 
 def _extras(dtb, inputs, torch, np, stream, records, den, skip):
@@ -339,16 +344,17 @@ def _cpu_baseline(w, budget_s: float):
     import oracle  # test infrastructure, used only for this leg
     u = w.grid()
     nt = oracle.default_threads()
+    fn = oracle.j2d9pt_f64 if w.pts == 9 else oracle.j2d5pt_f64
     steps, t0 = 0, time.perf_counter()
     chunk = max(1, min(50, int(2e9 // (w.rows * w.cols))))
     while time.perf_counter() - t0 < budget_s and steps < w.T:
-        u = oracle.j2d5pt_f64(u, w.coeffs, chunk, nthreads=nt)
+        u = fn(u, w.coeffs, chunk, nthreads=nt)
         steps += chunk
     dt = time.perf_counter() - t0
     u1 = w.grid()
     s1, t1 = 0, time.perf_counter()
     while time.perf_counter() - t1 < budget_s / 4 and s1 < w.T:
-        u1 = oracle.j2d5pt_f64(u1, w.coeffs, 1, nthreads=1)
+        u1 = fn(u1, w.coeffs, 1, nthreads=1)
         s1 += 1
     dt1 = time.perf_counter() - t1
     model = ""
@@ -401,7 +407,7 @@ def main() -> int:
     u0 = torch.from_numpy(w.grid()).to(device="cuda", dtype=dt)
     g = u0.clone()
     stream = torch.cuda.current_stream()
-    plan = dtb.plan_for(g, w.T)
+    plan = dtb.plan_for(g, w.T, stencil=w.pts)
     desc = plan.describe()
     print(f"[bench] {w.name} plan {desc}", file=sys.stderr, flush=True)
 
@@ -431,7 +437,7 @@ def main() -> int:
 
     base = None
     if not args.no_step_baseline:
-        launches, graph_ms = _step_baseline(dtb, torch, stream, g, u0, w.coeffs, w.T, 3)
+        launches, graph_ms = _step_baseline(dtb, torch, stream, g, u0, w.coeffs, w.T, 3, w.pts)
         bms = min([launches] + (graph_ms or []))
         bval = updates / (bms / 1e3) / 1e9
         b = 8 if w.dtype == "f64" else 4
@@ -457,21 +463,22 @@ def main() -> int:
     records = _accuracy_records()
 
     peak = PEAK_FP64_VECTOR_TFLOPS if w.dtype == "f64" else PEAK_FP32_VECTOR_TFLOPS
-    achieved = FLOPS_PER_UPDATE * updates / (avg_ms / 1e3) / 1e12
+    flops = FLOPS_PER_UPDATE9 if w.pts == 9 else FLOPS_PER_UPDATE
+    achieved = flops * updates / (avg_ms / 1e3) / 1e12
     kname = {2: "k_dtb", 3: "k_dtb_sweep"}.get(desc["path"], "k_step")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": _recorded_traffic(kname, w.name),
             "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
             "launch_ms_min_median_max": [round(min(kern_ms), 4), round(float(np.median(kern_ms)), 4),
                                          round(max(kern_ms), 4)],
-            "algorithmic_flops_per_launch": FLOPS_PER_UPDATE * updates}
-    context = _rooflines(value, w.dtype, desc, w.T, updates, avg_ms, den)
+            "algorithmic_flops_per_launch": flops * updates}
+    context = _rooflines(value, w.dtype, desc, w.T, updates, avg_ms, den, flops)
     context["error_vs_oracle"] = _error_for(records, w.name, w.dtype)
 
     phases = None
     if args.phase_clocks:
         # Where a step's time goes, from per-workgroup phase clocks of the same plan shape.
-        tp = dtb.plan_for(g, w.T, debug=dtb.DEBUG_TIMING)
+        tp = dtb.plan_for(g, w.T, debug=dtb.DEBUG_TIMING, stencil=w.pts)
         g.copy_(u0)
         tp.run(g, w.coeffs, w.T)
         tp.check()

@@ -21,6 +21,15 @@
  * Coefficients are passed as five doubles in the order (c, n, s, e, w).  They
  * need not sum to 1 and are copied at the call.  DTB_F32 rounds them to float.
  *
+ * The 3 x 3 box (j2d9pt), the next stencil shape of the same method (a plan
+ * made with dtb_plan_opts.stencil = 9): every interior cell becomes the
+ * weighted sum of the 3 x 3 block of cells centred on it,
+ *     sw*u[i-1][j-1] + s*u[i-1][j] + se*u[i-1][j+1] + w*u[i][j-1] + c*u[i][j]
+ *   + e*u[i][j+1] + nw*u[i+1][j-1] + n*u[i+1][j] + ne*u[i+1][j+1],
+ * with the nine coefficients passed in that order (sw, s, se, w, c, e, nw, n,
+ * ne) and summed in that order (fused multiply-adds by default, separately
+ * rounded products with exact = 1).  The halo's corner cells are read.
+ *
  * Arithmetic: by default each cell is a chain of one multiply and four fused
  * multiply-adds in the order W, E, S, C, N.  With dtb_plan_opts.exact = 1
  * the products are rounded separately and summed left to right in that same
@@ -96,6 +105,9 @@ typedef struct {
     int32_t sync;        /* resident path, what a workgroup waits for at an exchange: 0 = the workgroups
                             whose cells it reads (neighbour epoch flags); 1 = every workgroup, at a
                             device-wide barrier (the grid-level barrier of Section 3.2; for comparison) */
+    int32_t stencil;     /* 0 or 5: j2d5pt (five coefficients); 9: the 3 x 3 box (nine coefficients, see
+                            above): step, resident and sweep paths, 8 waves, neighbour flags; register
+                            tiles FP64 4 x 8 and FP32 4 x 16 per lane (rows_per_lane 8 / 16) */
 } dtb_plan_opts;
 
 /* Debug bits for dtb_plan_opts.debug_flags. */
@@ -138,14 +150,16 @@ dtb_status dtb_plan(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, 
 
 /*
  * Advance grid->data by T steps in place with an explicit plan (Listing 1's
- * update repeated T times, Section 3.1 and Figure 1).  The grid's
+ * update repeated T times, Section 3.1 and Figure 1; the 3 x 3 box for a plan
+ * made with stencil = 9).  coeffs: five doubles (c, n, s, e, w), or nine (sw,
+ * s, se, w, c, e, nw, n, ne) for a box plan.  The grid's
  * rows, cols, pitch and dtype must match the plan.  T == 0 returns DTB_OK
  * without launching.  The plan's workspace serves one run at a time: a call
  * on another stream than the plan's previous run waits for that run first
  * (outside stream capture; inside it, runs are ordered by the capturing
  * stream).  Calls on other plans may overlap.  Does not allocate.
  */
-dtb_status dtb_run_plan(dtb_plan_t plan, const dtb_grid* grid, const double coeffs[5], int64_t T,
+dtb_status dtb_run_plan(dtb_plan_t plan, const dtb_grid* grid, const double* coeffs, int64_t T,
                         void* stream);
 
 /*
@@ -205,7 +219,8 @@ dtb_status dtb_plan_timing(dtb_plan_t plan, uint64_t* out, int32_t n, void* stre
 /*
  * Describe a plan: fills up to `n` int64 values in this order: path,
  * workgroups, ghost_k, depth_D, ext_rows, ext_cols, tiles_rows, tiles_cols,
- * rows_per_lane, cols_per_lane, big_tiles, exact, waves, sync.  Returns DTB_OK.
+ * rows_per_lane, cols_per_lane, big_tiles, exact, waves, sync, stencil (5 or 9).
+ * Returns DTB_OK.
  */
 dtb_status dtb_plan_describe(dtb_plan_t plan, int64_t* values, int32_t n);
 

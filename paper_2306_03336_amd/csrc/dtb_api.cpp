@@ -51,6 +51,7 @@ struct dtb_plan_s {
     int device = -1;
     int64_t rows = 0, cols = 0, pitch = 0;
     int dtype = 0;
+    int pts = 5;  // stencil: 5 (j2d5pt) or 9 (the 3 x 3 box)
     int path = DTB_PATH_STEP;
     bool fma = true;
     // one-step path
@@ -112,6 +113,7 @@ dtb_status check_opts(const dtb_plan_opts* o)
     if (!o) return DTB_OK;
     if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_OVERLAPPED) return DTB_ERR_INVALID_ARG;
     if (o->sync != 0 && o->sync != 1) return DTB_ERR_INVALID_ARG;
+    if (o->stencil != 0 && o->stencil != 5 && o->stencil != 9) return DTB_ERR_INVALID_ARG;
     if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0) return DTB_ERR_INVALID_ARG;
     if (o->waves != 0 && o->waves != 4 && o->waves != 8) return DTB_ERR_INVALID_ARG;
     if (o->exact != 0 && o->exact != 1) return DTB_ERR_INVALID_ARG;
@@ -121,11 +123,16 @@ dtb_status check_opts(const dtb_plan_opts* o)
     return DTB_OK;
 }
 
+int stencil_points(const dtb_plan_opts& o) { return o.stencil == 9 ? 9 : 5; }
+
 // A requested tile instance must exist: FP64 8, 12, 16, 24 rows per lane and,
 // with 4 waves per workgroup, 24 rows on the resident path only; FP32 8, 16,
-// 24, 28 rows with 8 waves.  Checked before any HIP call.
+// 24, 28 rows with 8 waves.  The box stencil: FP64 8 and FP32 16 rows, 8
+// waves, resident and sweep paths, neighbour flags.  Checked before any HIP call.
 dtb_status check_instance(const dtb_plan_opts& o, int dtype)
 {
+    const int pts = stencil_points(o);
+    if (pts == 9 && (o.path == DTB_PATH_OVERLAPPED || o.waves == 4 || o.sync == 1)) return DTB_ERR_UNSUPPORTED;
     if (o.path == DTB_PATH_STEP) return DTB_OK;
     if (o.waves == 4 && (dtype != DTB_F64 || o.path == DTB_PATH_SWEEP || o.path == DTB_PATH_OVERLAPPED ||
                          (o.rows_per_lane != 0 && o.rows_per_lane != 24)))
@@ -134,9 +141,9 @@ dtb_status check_instance(const dtb_plan_opts& o, int dtype)
     if (o.sync == 1 && (o.path == DTB_PATH_SWEEP || o.path == DTB_PATH_OVERLAPPED || o.tune)) return DTB_ERR_UNSUPPORTED;
     if (o.rows_per_lane > 0) {
         int C = 0, waves = 0;
-        const void* f = o.path == DTB_PATH_SWEEP ? dtb_sweep_kernel(dtype, o.rows_per_lane, true, false, false, &C, &waves)
+        const void* f = o.path == DTB_PATH_SWEEP ? dtb_sweep_kernel(dtype, o.rows_per_lane, true, false, false, &C, &waves, pts)
                       : o.path == DTB_PATH_OVERLAPPED ? dtb_ovl_kernel(dtype, o.rows_per_lane, true, false, false, &C, &waves)
-                      : dtb_kernel(dtype, o.rows_per_lane, true, false, false, &C, &waves, o.waves);
+                      : dtb_kernel(dtype, o.rows_per_lane, true, false, false, &C, &waves, o.waves, pts);
         if (!f) return DTB_ERR_UNSUPPORTED;
     }
     return DTB_OK;
@@ -163,6 +170,7 @@ constexpr int64_t kSweepSpillSlack = 32;
 bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o, int n_cu, bool fma,
                      Layout* best_layout, const void** best_func, bool* colmask, bool* rowcheck)
 {
+    const int pts = stencil_points(o);
     double best = 1e300;
     bool found = false;
     // Every ring depth from 2 to 24: with all tiles running side by side, the
@@ -180,7 +188,7 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
         for (int k : ks) {
             if (o.waves != want_waves && !(o.waves == 0 && want_waves == 8)) continue;
             int C = 0, waves = 0;
-            const void* f0 = dtb_kernel(dtype, R, fma, false, false, &C, &waves, want_waves);
+            const void* f0 = dtb_kernel(dtype, R, fma, false, false, &C, &waves, want_waves, pts);
             if (!f0) continue;
             Layout L;
             // No more tiles than can be co-resident (at most two workgroups per compute unit): larger
@@ -189,14 +197,14 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
                               true, 2 * n_cu))
                 continue;
             const bool cm = L.cols.narrow, rc = L.rows.narrow;
-            const void* f = dtb_kernel(dtype, R, fma, cm, rc, &C, &waves, want_waves);
+            const void* f = dtb_kernel(dtype, R, fma, cm, rc, &C, &waves, want_waves, pts);
             if (spills(f)) continue;
             int occ = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) != hipSuccess) continue;
             int cap = occ * n_cu;
             if (o.max_wg > 0) cap = std::min(cap, o.max_wg);
             if (L.nwg > cap) continue;
-            const double cost = layout_cost(L, occ, n_cu, dtype == DTB_F64 ? 8 : 4);
+            const double cost = layout_cost(L, occ, n_cu, dtype == DTB_F64 ? 8 : 4, pts);
             if (cost < best) {
                 best = cost;
                 *best_layout = L;
@@ -214,10 +222,10 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
 // D steps on the whole chip (VALU time of one register tile per step), one
 // exchange every k steps, one device-wide barrier, and its HBM traffic (load
 // of the computed region, store of the valid part) once per D steps.
-double sweep_step_us(const SweepPlan& sp, int dtype)
+double sweep_step_us(const SweepPlan& sp, int dtype, int pts)
 {
     const int eb = dtype == DTB_F64 ? 8 : 4;
-    const double t_step = tile_step_time_us(sp.ER, sp.EC, eb);
+    const double t_step = tile_step_time_us(sp.ER, sp.EC, eb, pts);
     const double t_exch = exchange_time_us(sp.ER, sp.EC, sp.R, sp.C, eb, exchange_staged(sp.R, sp.C, eb, sp.k));
     const double t_bar = 10.0;  // device-wide barrier plus the tile load's latency, per big tile
     const double hbm_bytes_per_us = 4.0e6;
@@ -289,6 +297,7 @@ bool choose_overlapped(int64_t rows, int64_t cols, int dtype, const dtb_plan_opt
 bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o, int n_cu, bool fma, SweepPlan* best,
                   const void** best_func, bool* colmask, bool* rowcheck, int* nwg_cap)
 {
+    const int pts = stencil_points(o);
     double best_t = 1e300;
     bool found = false;
     std::vector<int> ks, Ds;
@@ -299,9 +308,9 @@ bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o,
     for (int R : kDtbRowsPerLane) {
         if (o.rows_per_lane > 0 && o.rows_per_lane != R) continue;
         int C = 0, waves = 0;
-        if (!dtb_sweep_kernel(dtype, R, fma, false, false, &C, &waves)) continue;
+        if (!dtb_sweep_kernel(dtype, R, fma, false, false, &C, &waves, pts)) continue;
         const bool cm = cols < kWaveSize * C, rc = rows < waves * R;
-        const void* f = dtb_sweep_kernel(dtype, R, fma, cm, rc, &C, &waves);
+        const void* f = dtb_sweep_kernel(dtype, R, fma, cm, rc, &C, &waves, pts);
         const int64_t sb = spill_bytes(f);
         if (sb < 0 || sb > kSweepSpillSlack) continue;
         const double penalty = sb > 0 ? 1.1 : 1.0;
@@ -314,7 +323,7 @@ bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o,
             for (int D : Ds) {
                 SweepPlan sp;
                 if (!plan_sweep(rows, cols, R, C, waves, k, D, cap, kNumXcd, &sp)) continue;
-                const double t = sweep_step_us(sp, dtype) * penalty;
+                const double t = sweep_step_us(sp, dtype, pts) * penalty;
                 if (t < best_t) {
                     best_t = t;
                     *best = std::move(sp);
@@ -343,7 +352,8 @@ std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune;
 bool g_tune_loaded = false;
 
-std::string tune_key(int64_t rows, int64_t cols, int64_t pitch, int dtype, int exact, int64_t T_hint, int max_wg)
+std::string tune_key(int64_t rows, int64_t cols, int64_t pitch, int dtype, int pts, int exact, int64_t T_hint,
+                     int max_wg)
 {
     hipDeviceProp_t prop{};
     int dev = 0;
@@ -353,8 +363,8 @@ std::string tune_key(int64_t rows, int64_t cols, int64_t pitch, int dtype, int e
     int tb = 0;
     while ((int64_t(1) << tb) < T_hint && tb < 62) ++tb;
     char buf[256];
-    snprintf(buf, sizeof(buf), "%lld,%lld,%lld,%d,%d,%d,%d,%s,%d", (long long)rows, (long long)cols, (long long)pitch,
-             dtype, exact, tb, max_wg, prop.gcnArchName, prop.multiProcessorCount);
+    snprintf(buf, sizeof(buf), "%lld,%lld,%lld,%d,%d,%d,%d,%d,%s,%d", (long long)rows, (long long)cols,
+             (long long)pitch, dtype, pts, exact, tb, max_wg, prop.gcnArchName, prop.multiProcessorCount);
     return buf;
 }
 
@@ -395,38 +405,39 @@ std::vector<std::pair<double, TuneChoice>> tune_candidates(int64_t rows, int64_t
 {
     std::vector<std::pair<double, TuneChoice>> out;
     const bool fma = o.exact == 0;
+    const int pts = stencil_points(o);
     for (int R : kDtbRowsPerLane) {
         if (o.rows_per_lane > 0 && o.rows_per_lane != R) continue;
         int C = 0, waves = 0;
-        if (!dtb_kernel(dtype, R, fma, false, false, &C, &waves)) continue;
+        if (!dtb_kernel(dtype, R, fma, false, false, &C, &waves, 0, pts)) continue;
         for (int k : {2, 4, 6, 8, 10, 12, 16, 20, 24}) {
             if (o.ghost_k > 0 && o.ghost_k != k) continue;
             if (o.path == DTB_PATH_AUTO || o.path == DTB_PATH_RESIDENT) {
                 Layout L;
                 if (build_layout(rows, cols, interior(rows, cols), interior(rows, cols), R, C, waves, k, kNumXcd, 0,
                                  0, &L, true, 2 * n_cu)) {
-                    const void* f = dtb_kernel(dtype, R, fma, L.cols.narrow, L.rows.narrow, &C, &waves);
+                    const void* f = dtb_kernel(dtype, R, fma, L.cols.narrow, L.rows.narrow, &C, &waves, 0, pts);
                     int occ = 0;
                     if (f && !spills(f) &&
                         hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) == hipSuccess) {
                         int cap = occ * n_cu;
                         if (o.max_wg > 0) cap = std::min(cap, o.max_wg);
                         if (L.nwg <= cap)
-                            out.push_back({layout_cost(L, occ, n_cu, dtype == DTB_F64 ? 8 : 4),
+                            out.push_back({layout_cost(L, occ, n_cu, dtype == DTB_F64 ? 8 : 4, pts),
                                            TuneChoice{DTB_PATH_RESIDENT, R, k, 0}});
                     }
                 }
             }
             if (o.path == DTB_PATH_SWEEP || (o.path == DTB_PATH_AUTO && out.empty())) {
                 const bool cm = cols < kWaveSize * C, rc = rows < waves * R;
-                const void* f = dtb_sweep_kernel(dtype, R, fma, cm, rc, &C, &waves);
+                const void* f = dtb_sweep_kernel(dtype, R, fma, cm, rc, &C, &waves, pts);
                 if (!f || spills(f)) continue;
                 const int cap = o.max_wg > 0 ? std::min(n_cu, o.max_wg) : n_cu;
                 for (int D : {16, 32, 48, 64, 96, 128, 192}) {
                     if (o.depth_D > 0 && o.depth_D != D) continue;
                     SweepPlan sp;
                     if (!plan_sweep(rows, cols, R, C, waves, k, D, cap, kNumXcd, &sp)) continue;
-                    out.push_back({sweep_step_us(sp, dtype), TuneChoice{DTB_PATH_SWEEP, R, k, D}});
+                    out.push_back({sweep_step_us(sp, dtype, pts), TuneChoice{DTB_PATH_SWEEP, R, k, D}});
                 }
             }
         }
@@ -450,7 +461,8 @@ double time_candidate(int64_t rows, int64_t cols, int64_t pitch, int dtype, cons
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     double best = 1e300;
-    const double coeffs[5] = {0.2, 0.2, 0.2, 0.2, 0.2};
+    double coeffs[9];
+    for (double& c : coeffs) c = 1.0 / stencil_points(o);  // weights summing to 1: the zero grid stays zero
     const dtb_grid g{scratch, rows, cols, pitch};
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
         hipEventCreate(&e1) == hipSuccess) {
@@ -479,7 +491,7 @@ dtb_status tune_plan(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
 {
     DeviceInfo di;
     if (!device_info(&di)) return DTB_ERR_HIP;
-    const std::string key = tune_key(rows, cols, pitch, dtype, o.exact, T_hint, o.max_wg);
+    const std::string key = tune_key(rows, cols, pitch, dtype, stencil_points(o), o.exact, T_hint, o.max_wg);
     TuneChoice choice;
     bool have = false;
     {
@@ -552,6 +564,7 @@ dtb_status plan_impl(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch,
     p->pitch = pitch;
     p->dtype = dtype;
     p->fma = o.exact == 0;
+    p->pts = stencil_points(o);
     p->debug = o.debug_flags;
     const size_t bytes = (size_t)(rows + 2) * (size_t)pitch * elem_size(dtype);
 
@@ -657,7 +670,8 @@ dtb_status run_step(dtb_plan_t p, void* data, const double* coeffs, int64_t T, h
     void* in = data;
     void* out = p->ws;
     for (int64_t t = 0; t < T; ++t) {
-        if (launch_step(p->dtype, p->fma, in, out, p->pitch, rows, cols, coeffs, st) != hipSuccess) return DTB_ERR_HIP;
+        if (launch_step(p->dtype, p->fma, in, out, p->pitch, rows, cols, coeffs, st, p->pts) != hipSuccess)
+            return DTB_ERR_HIP;
         std::swap(in, out);
     }
     if (in != data) {
@@ -706,7 +720,7 @@ dtb_status run_resident(dtb_plan_t p, void* data, const double* coeffs, int64_t 
     P.grid_sync = p->grid_sync ? 1 : 0;
     P.bar = p->d_bar;
     if (p->grid_sync && launch_reset_counter(p->d_bar, st) != hipSuccess) return DTB_ERR_HIP;
-    for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
+    for (int i = 0; i < p->pts; ++i) P.coeffs[i] = coeffs[i];
     const WgDesc* wgs = p->d_wgs;
     uint32_t* flags = p->d_flags;
     int* err = p->d_err;
@@ -737,7 +751,7 @@ dtb_status run_overlapped_path(dtb_plan_t p, void* data, const double* coeffs, i
     P.fma = p->fma ? 1 : 0;
     P.narrow_cols = p->colmask ? 1 : 0;
     P.narrow_rows = p->rowcheck ? 1 : 0;
-    for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
+    for (int i = 0; i < p->pts; ++i) P.coeffs[i] = coeffs[i];
     const WgDesc* wgs = p->d_wgs;
     void* bufs[2] = {data, p->ws};
     const dim3 grid(p->layout.nwg), block(p->layout.waves * kWaveSize);
@@ -783,7 +797,7 @@ dtb_status run_sweep(dtb_plan_t p, void* data, const double* coeffs, int64_t T, 
     P.debug = p->debug;
     P.timing = p->d_timing;
     P.direct_xchg = (p->debug & DTB_DEBUG_DIRECT_XCHG) ? 1 : 0;
-    for (int i = 0; i < 5; ++i) P.coeffs[i] = coeffs[i];
+    for (int i = 0; i < p->pts; ++i) P.coeffs[i] = coeffs[i];
     SweepArgs S{};
     S.bufs[0] = data;
     S.bufs[1] = p->ws;
@@ -1073,7 +1087,7 @@ dtb_status dtb_plan(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, 
     return plan_impl(out, rows, cols, pitch, (int)dtype, T_hint, opts);
 }
 
-dtb_status dtb_run_plan(dtb_plan_t plan, const dtb_grid* grid, const double coeffs[5], int64_t T, void* stream)
+dtb_status dtb_run_plan(dtb_plan_t plan, const dtb_grid* grid, const double* coeffs, int64_t T, void* stream)
 {
     return run_plan_impl(plan, grid, coeffs, T, stream);
 }
@@ -1178,7 +1192,7 @@ dtb_status dtb_plan_describe(dtb_plan_t p, int64_t* v, int32_t n)
     const bool sw = p->path == DTB_PATH_SWEEP, ov = p->path == DTB_PATH_OVERLAPPED;
     const int64_t all[] = {p->path, sw ? p->nwg_launch : L.nwg, ov ? 0 : L.k, sw ? p->sweep.D : (ov ? p->ovl_D : 0), L.ER, L.EC,
                            L.rows.parts, L.cols.parts, L.R, L.C, sw ? (int64_t)p->sweep.tiles.size() : 0,
-                           p->fma ? 0 : 1, L.waves, p->grid_sync ? 1 : 0};
+                           p->fma ? 0 : 1, L.waves, p->grid_sync ? 1 : 0, p->pts};
     for (int32_t i = 0; i < n && i < (int32_t)(sizeof(all) / sizeof(all[0])); ++i) v[i] = all[i];
     return DTB_OK;
 }

@@ -1,4 +1,5 @@
-// dtb_kernels.hip -- gfx950 kernels for the j2d5pt iterative stencil.
+// dtb_kernels.hip -- gfx950 kernels for the j2d5pt iterative stencil (and the
+// one-step baseline of the 3 x 3 box, j2d9pt).
 //
 // The update (Listing 1 of Zhang et al., GPGPU '23): every interior cell
 // becomes w*W + e*E + s*S + c*C + n*N of the previous step's values, with
@@ -147,6 +148,100 @@ __global__ __launch_bounds__(256) void k_step_vec(const T* __restrict__ in, T* _
     }
 }
 
+// ---- the 3 x 3 box (j2d9pt): the same two one-step kernels.  Every output
+// cell is the weighted sum of its 3 x 3 block of the previous step's values
+// (weights in the order sw, s, se, w, c, e, nw, n, ne; S = row i-1), products
+// summed in that order.
+
+// Thread (tx, ty) owns column j and kStepIlp consecutive rows, and keeps the
+// three columns j-1, j, j+1 of those rows and the rows above and below in
+// registers.
+template <typename T, bool FMA>
+__global__ __launch_bounds__(256) void k_step9(const T* __restrict__ in, T* __restrict__ out, int64_t pitch,
+                                               int rows, int cols, Coef9<T> k)
+{
+    const int j = blockIdx.x * 64 + threadIdx.x + 1;
+    const int i0 = (blockIdx.y * 4 + threadIdx.y) * kStepIlp + 1;
+    if (j > cols || i0 > rows) return;
+    T cw[kStepIlp + 2], cm[kStepIlp + 2], ce[kStepIlp + 2];
+#pragma unroll
+    for (int q = 0; q < kStepIlp + 2; ++q) {
+        const int i = i0 - 1 + q;
+        const T* row = in + (int64_t)i * pitch;
+        const bool ok = i <= rows + 1;
+        cw[q] = ok ? row[j - 1] : T(0);
+        cm[q] = ok ? row[j] : T(0);
+        ce[q] = ok ? row[j + 1] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kStepIlp; ++q) {
+        const int i = i0 + q;
+        if (i <= rows) {
+            const T a[9] = {cw[q], cm[q], ce[q], cw[q + 1], cm[q + 1], ce[q + 1], cw[q + 2], cm[q + 2], ce[q + 2]};
+            out[(int64_t)i * pitch + j] = j2d9pt<FMA>(a, k);
+        }
+    }
+}
+
+// 16-byte groups as in k_step_vec; a lane's west/east neighbours in each of
+// the three rows come from the neighbouring lanes (lanes 0 and 63 read theirs
+// from memory).
+template <typename T, bool FMA>
+__global__ __launch_bounds__(256) void k_step9_vec(const T* __restrict__ in, T* __restrict__ out, int64_t pitch,
+                                                   int rows, int cols, Coef9<T> k)
+{
+    constexpr int V = 16 / (int)sizeof(T);
+    using VT = std::conditional_t<sizeof(T) == 8, double2, float4>;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int j0 = (blockIdx.x * 64 + lane) * V;
+    const int i0 = (blockIdx.y * 4 + wave) * kStepRows + 1;
+    if (i0 > rows) return;  // the whole wave
+    const bool inrow = j0 <= cols + 1;
+    // c[q][0] and c[q][V + 1]: the west and east neighbours of the group in row i0 - 1 + q.
+    T c[kStepRows + 2][V + 2];
+#pragma unroll
+    for (int q = 0; q < kStepRows + 2; ++q) {
+        const int i = i0 - 1 + q;
+        const bool ok = inrow && i <= rows + 1;
+        VT v{};
+        if (ok) v = *(const VT*)(in + (int64_t)i * pitch + j0);
+        const T* e = (const T*)&v;
+#pragma unroll
+        for (int x = 0; x < V; ++x) c[q][x + 1] = e[x];
+        T wv = lane_shr1(c[q][V]);
+        T ev = lane_shl1(c[q][1]);
+        if (lane == 0 && j0 >= 1 && ok) wv = in[(int64_t)i * pitch + j0 - 1];
+        if (lane == 63 && j0 + V <= cols + 1 && ok) ev = in[(int64_t)i * pitch + j0 + V];
+        c[q][0] = wv;
+        c[q][V + 1] = ev;
+    }
+#pragma unroll
+    for (int q = 0; q < kStepRows; ++q) {
+        const int i = i0 + q;
+        if (i > rows) break;  // uniform: the wave's rows
+        T r[V];
+#pragma unroll
+        for (int x = 0; x < V; ++x) {
+            const T a[9] = {c[q][x], c[q][x + 1], c[q][x + 2], c[q + 1][x], c[q + 1][x + 1], c[q + 1][x + 2],
+                            c[q + 2][x], c[q + 2][x + 1], c[q + 2][x + 2]};
+            r[x] = j2d9pt<FMA>(a, k);
+        }
+        T* orow = out + (int64_t)i * pitch;
+        if (j0 >= 1 && j0 + V - 1 <= cols) {
+            VT v;
+            T* e = (T*)&v;
+#pragma unroll
+            for (int x = 0; x < V; ++x) e[x] = r[x];
+            *(VT*)(orow + j0) = v;
+        } else if (inrow) {
+#pragma unroll
+            for (int x = 0; x < V; ++x)
+                if (j0 + x >= 1 && j0 + x <= cols) orow[j0 + x] = r[x];
+        }
+    }
+}
+
 // Copies the interior of src into dst (used when an odd number of one-step
 // launches leaves the result in the workspace).
 template <typename T>
@@ -186,6 +281,26 @@ __global__ void k_reset_counter(uint32_t* bar)
 // ============================================================================ host-side launchers
 
 template <typename T>
+static hipError_t launch_step9_t(bool fma, const void* in, void* out, int64_t pitch, int rows, int cols,
+                                 const double* coeffs, hipStream_t st)
+{
+    Coef9<T> k;
+    for (int q = 0; q < 9; ++q) k.k[q] = (T)coeffs[q];
+    constexpr int V = 16 / (int)sizeof(T);
+    if ((uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0 && pitch % V == 0) {
+        dim3 grid((unsigned)((cols + 2 + 64 * V - 1) / (64 * V)), (unsigned)((rows + 4 * kStepRows - 1) / (4 * kStepRows)));
+        if (fma) hipLaunchKernelGGL((k_step9_vec<T, true>), grid, dim3(256), 0, st, (const T*)in, (T*)out, pitch, rows, cols, k);
+        else hipLaunchKernelGGL((k_step9_vec<T, false>), grid, dim3(256), 0, st, (const T*)in, (T*)out, pitch, rows, cols, k);
+        return hipGetLastError();
+    }
+    dim3 block(64, 4);
+    dim3 grid((cols + 63) / 64, (rows + 4 * kStepIlp - 1) / (4 * kStepIlp));
+    if (fma) hipLaunchKernelGGL((k_step9<T, true>), grid, block, 0, st, (const T*)in, (T*)out, pitch, rows, cols, k);
+    else hipLaunchKernelGGL((k_step9<T, false>), grid, block, 0, st, (const T*)in, (T*)out, pitch, rows, cols, k);
+    return hipGetLastError();
+}
+
+template <typename T>
 static hipError_t launch_step_t(bool fma, const void* in, void* out, int64_t pitch, int rows, int cols,
                                 const double* coeffs, hipStream_t st)
 {
@@ -205,8 +320,11 @@ static hipError_t launch_step_t(bool fma, const void* in, void* out, int64_t pit
 }
 
 hipError_t launch_step(int dtype, bool fma, const void* in, void* out, int64_t pitch, int rows, int cols,
-                       const double* coeffs, hipStream_t st)
+                       const double* coeffs, hipStream_t st, int pts)
 {
+    if (pts == 9)
+        return dtype == 0 ? launch_step9_t<double>(fma, in, out, pitch, rows, cols, coeffs, st)
+                          : launch_step9_t<float>(fma, in, out, pitch, rows, cols, coeffs, st);
     return dtype == 0 ? launch_step_t<double>(fma, in, out, pitch, rows, cols, coeffs, st)
                       : launch_step_t<float>(fma, in, out, pitch, rows, cols, coeffs, st);
 }
@@ -244,12 +362,26 @@ DTB_DECLARE(pick_f32_r8)
 DTB_DECLARE(pick_f32_r16)
 DTB_DECLARE(pick_f32_r24)
 DTB_DECLARE(pick_f32_r28)
+DTB_DECLARE(pick_box_f64_r8)
+DTB_DECLARE(pick_box_f32_r16)
 #undef DTB_DECLARE
 
 // kind: 0 resident, 1 tile-serial sweep, 2 overlapped per-workgroup blocking.
+// pts: 5 (j2d5pt) or 9 (the 3 x 3 box: FP64 4 x 8 and FP32 4 x 16 per lane,
+// resident and sweep kernels only).
 static const void* dtb_kernel_any(int kind, int dtype, int R, int want_waves, bool fma, bool colmask, bool rowcheck,
-                                  int* C, int* waves)
+                                  int* C, int* waves, int pts)
 {
+    if (pts == 9) {
+        if (want_waves != 0 && want_waves != 8) return nullptr;
+        *waves = 8;
+        *C = 4;
+        if (kind == 2) return nullptr;
+        if (dtype == 0 && R == 8) return pick_box_f64_r8(kind, fma, colmask, rowcheck);
+        if (dtype == 1 && R == 16) return pick_box_f32_r16(kind, fma, colmask, rowcheck);
+        return nullptr;
+    }
+    if (pts != 5) return nullptr;
     if (want_waves == 4) {
         // Half-height workgroups, two per compute unit (resident path only).
         *waves = 4;
@@ -280,19 +412,20 @@ static const void* dtb_kernel_any(int kind, int dtype, int R, int want_waves, bo
     }
 }
 
-const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves, int want_waves)
+const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves, int want_waves,
+                       int pts)
 {
-    return dtb_kernel_any(0, dtype, R, want_waves, fma, colmask, rowcheck, C, waves);
+    return dtb_kernel_any(0, dtype, R, want_waves, fma, colmask, rowcheck, C, waves, pts);
 }
 
-const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
+const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves, int pts)
 {
-    return dtb_kernel_any(1, dtype, R, 8, fma, colmask, rowcheck, C, waves);
+    return dtb_kernel_any(1, dtype, R, 8, fma, colmask, rowcheck, C, waves, pts);
 }
 
 const void* dtb_ovl_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves)
 {
-    return dtb_kernel_any(2, dtype, R, 8, fma, colmask, rowcheck, C, waves);
+    return dtb_kernel_any(2, dtype, R, 8, fma, colmask, rowcheck, C, waves, 5);
 }
 
 hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st)

@@ -7,23 +7,28 @@
 
 namespace dtb {
 
+// One step of the untiled baseline; pts 5: j2d5pt (five coefficients c, n, s,
+// e, w), 9: the 3 x 3 box (nine, sw .. ne).
 hipError_t launch_step(int dtype, bool fma, const void* in, void* out, int64_t pitch, int rows, int cols,
-                       const double* coeffs, hipStream_t st);
+                       const double* coeffs, hipStream_t st, int pts = 5);
 hipError_t launch_copy_interior(int dtype, const void* src, void* dst, int64_t pitch, int rows, int cols,
                                 hipStream_t st);
 hipError_t launch_copy_halo(int dtype, const void* src, void* dst, int64_t pitch, int rows, int cols,
                             hipStream_t st);
 
-// The DTB kernel for (dtype, rows per lane R, variant), or nullptr when that R
-// is not instantiated.  *C receives the columns per lane and *waves the waves
-// per workgroup of the instance.  want_waves: 0 or 8 for the standard
-// 8-wave workgroups, 4 for the half-height instances (FP64 R = 24 only).
+// The DTB kernel for (dtype, rows per lane R, variant, stencil), or nullptr
+// when that R is not instantiated.  *C receives the columns per lane and
+// *waves the waves per workgroup of the instance.  want_waves: 0 or 8 for the
+// standard 8-wave workgroups, 4 for the half-height instances (FP64 R = 24
+// only).  pts: 5 (j2d5pt) or 9 (the 3 x 3 box: FP64 R = 8, FP32 R = 16, both
+// with 4 columns per lane).
 const void* dtb_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves,
-                       int want_waves = 0);
+                       int want_waves = 0, int pts = 5);
 
 // The tile-serial sweep kernel of the same instance (arguments: ProbDesc,
 // SweepArgs, descriptor table, flags, error word, spin limit).
-const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves);
+const void* dtb_sweep_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves,
+                             int pts = 5);
 
 // Arguments of the sweep kernel besides the problem.
 struct SweepArgs {

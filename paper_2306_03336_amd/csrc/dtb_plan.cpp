@@ -232,9 +232,11 @@ bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st
 // microseconds of fixed latency (store completion, flag round trip, load
 // latency) plus a part that grows with the number of border cells moved
 // lane by lane.
-double tile_step_time_us(int ER, int EC, int elem_bytes)
+double tile_step_time_us(int ER, int EC, int elem_bytes, int pts)
 {
-    const double per_cell = elem_bytes == 8 ? (EC <= 2 * kWaveSize ? 56e-6 : 52e-6) : 39e-6;
+    double per_cell = elem_bytes == 8 ? (EC <= 2 * kWaveSize ? 56e-6 : 52e-6) : 39e-6;
+    // The box: nine products instead of five and six lane shifts per row instead of two.
+    if (pts == 9) per_cell *= 1.8;
     return (double)ER * EC * per_cell + 0.11;
 }
 
@@ -245,18 +247,19 @@ double exchange_time_us(int ER, int EC, int R, int C, int elem_bytes, bool stage
     return 4.0 + 0.15 * R * C;
 }
 
-double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes)
+double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes, int pts)
 {
-    return layout_cost_of(L.nwg, L.R, L.C, L.ER, L.EC, L.k, slots_per_cu, n_cu, elem_bytes);
+    return layout_cost_of(L.nwg, L.R, L.C, L.ER, L.EC, L.k, slots_per_cu, n_cu, elem_bytes, pts);
 }
 
-double layout_cost_of(int nwg, int R, int C, int ER, int EC, int k, int slots_per_cu, int n_cu, int elem_bytes)
+double layout_cost_of(int nwg, int R, int C, int ER, int EC, int k, int slots_per_cu, int n_cu, int elem_bytes,
+                      int pts)
 {
     const int slots = std::max(1, slots_per_cu) * std::max(1, n_cu);
     if (nwg > slots) return 1e300;
     const int per_cu = (nwg + n_cu - 1) / n_cu;
     const bool staged = exchange_staged(R, C, elem_bytes, k);
-    const double step = tile_step_time_us(ER, EC, elem_bytes);
+    const double step = tile_step_time_us(ER, EC, elem_bytes, pts);
     const double exch = exchange_time_us(ER, EC, R, C, elem_bytes, staged) / k;
     if (per_cu <= 1) return step + exch;
     // Several workgroups per compute unit: measured (2048^2 FP64, two

@@ -81,18 +81,19 @@ bool build_layout(int64_t rows, int64_t cols, const Region& cr, const Region& st
 inline Region interior(int64_t rows, int64_t cols) { return Region{1, (int)rows + 1, 1, (int)cols + 1}; }
 
 // Time model (microseconds), calibrated on MI355X with one workgroup per
-// compute unit: one time step of an ER x EC register tile, and one exchange
-// (publish, flag wait, ghost load) of such a tile, through the LDS staging
-// area or lane by lane.
-double tile_step_time_us(int ER, int EC, int elem_bytes);
+// compute unit: one time step of an ER x EC register tile (pts: 5 for j2d5pt,
+// 9 for the 3 x 3 box), and one exchange (publish, flag wait, ghost load) of
+// such a tile, through the LDS staging area or lane by lane.
+double tile_step_time_us(int ER, int EC, int elem_bytes, int pts = 5);
 double exchange_time_us(int ER, int EC, int R, int C, int elem_bytes, bool staged);
 
 // Model time of one step of a resident layout on n_cu compute units holding
 // slots_per_cu workgroups each: the compute units with the most tiles run
 // all their steps, and one exchange every k steps (the exchanges of
 // co-resident tiles overlap).  Infinite if the layout does not fit.
-double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes);
-double layout_cost_of(int nwg, int R, int C, int ER, int EC, int k, int slots_per_cu, int n_cu, int elem_bytes);
+double layout_cost(const Layout& L, int slots_per_cu, int n_cu, int elem_bytes, int pts = 5);
+double layout_cost_of(int nwg, int R, int C, int ER, int EC, int k, int slots_per_cu, int n_cu, int elem_bytes,
+                      int pts = 5);
 
 // ---- resident layout without allocation (the allocation-free entry point)
 

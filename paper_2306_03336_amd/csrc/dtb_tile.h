@@ -155,7 +155,10 @@ struct Geo {
     // zeros (what every other lane reads on the row-by-row halo path) -- for
     // the box stencil the halo values themselves, of the rows -1 .. ER.
     static constexpr int kEdgeElems = 2 * (WAVES + 2) * 2 * EC;
-    static constexpr int kHaloElems = (ER + 2) * 3;
+    // West/east halo values of the ER + 2 rows a tile's box stencil reaches (three
+    // slots; the 5-point stencil uses three of ER), rounded up to 16 bytes so
+    // that the staging area after it stays 16-byte aligned.
+    static constexpr int kHaloElems = ((ER + 2) * 3 * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
     // Exchange staging area for rings up to kStageK deep (deeper rings take
     // the direct per-lane path): a block of up to 2 * kStageK full-width rows
     // (EC cells each) and a block of ER side rows (kSide left cells, then
@@ -270,6 +273,14 @@ struct Tile {
     __device__ __forceinline__ void step(T (&src)[R][C], T (&dst)[R][C], int parity, int rows)
     {
         static_assert(R >= 2, "a wave holds at least two rows");
+        if constexpr (PTS == 9) step9<HALO_ROWS>(src, dst, parity, rows);
+        else step5<HALO_ROWS>(src, dst, parity, rows);
+    }
+
+    // One j2d5pt step (Listing 1's update on every cell of the register tile).
+    template <bool HALO_ROWS>
+    __device__ __forceinline__ void step5(T (&src)[R][C], T (&dst)[R][C], int parity, int rows)
+    {
         // Publish this wave's current top and bottom rows for the waves above and below.
         T* mytop = edge_row(parity, wave + 1, 0);
         T* mybot = edge_row(parity, wave + 1, 1);
@@ -311,55 +322,88 @@ struct Tile {
     __device__ __forceinline__ void any_row(T (&src)[R][C], T (&dst)[R][C], int r, const T (&top)[C],
                                             const T (&bot)[C], int rows)
     {
-        if constexpr (PTS == 9) row9<HALO_ROWS>(src, dst, r, top, bot, rows);
-        else row<HALO_ROWS>(src, dst, r, top, bot, rows);
+        row<HALO_ROWS>(src, dst, r, top, bot, rows);
     }
 
-    // Row r of one box-stencil step: src -> dst.  The three source rows r-1,
-    // r, r+1 (the neighbouring waves' rows top / bot at the wave's ends) and
-    // their west/east neighbours across lanes; lane 0 of a west-edge tile and
-    // lane 63 of an east-edge tile take the halo values of the three storage
-    // rows (corners included) as the shifts' fall-back.  The nine products in
-    // the weights' order (sw, s, se, w, c, e, nw, n, ne), as the oracle sums them.
+    // West/east halo value a lane's row shifts fall back to, of the storage row
+    // at halo index q (rows ext_r0 - 1 .. ext_r0 + ER): lane 0 of a west-edge
+    // tile and lane 63 of an east-edge tile get the halo, every other lane 0.
     template <bool HALO_ROWS>
-    __device__ __forceinline__ void row9(T (&src)[R][C], T (&dst)[R][C], int r, const T (&top)[C], const T (&bot)[C],
-                                         int rows)
+    __device__ __forceinline__ T halo_w(int q) const { return HALO_ROWS ? hbw[q] : bw; }
+    template <bool HALO_ROWS>
+    __device__ __forceinline__ T halo_e(int q) const { return HALO_ROWS ? hbe[q] : be; }
+
+    // One box-stencil step: src -> dst.  Same schedule as step() (edge rows
+    // published first, inner rows around the barrier, the wave's first and
+    // last rows last), but every source row's west and east lane shifts are
+    // taken once and shared by the three output rows that read them: two
+    // shifts per source row instead of six per output row.
+    template <bool HALO_ROWS>
+    __device__ __forceinline__ void step9(T (&src)[R][C], T (&dst)[R][C], int parity, int rows)
+    {
+        T* mytop = edge_row(parity, wave + 1, 0);
+        T* mybot = edge_row(parity, wave + 1, 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            mytop[edge_pos(lane, c)] = src[0][c];
+            mybot[edge_pos(lane, c)] = src[R - 1][c];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // the stores issue first
+        const int q0 = wave * R + 1;  // halo index of this wave's row 0
+        T xw[R], xe[R];               // per source row: west neighbour of slot 0, east neighbour of slot C-1
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            xw[q] = wave_shr1_or(halo_w<HALO_ROWS>(q0 + q), src[q][C - 1]);
+            xe[q] = wave_shl1_or(halo_e<HALO_ROWS>(q0 + q), src[q][0]);
+        }
+        constexpr int kHalf = R / 2;
+#pragma unroll
+        for (int r = 1; r < kHalf; ++r)
+            box_row(src[r - 1], xw[r - 1], xe[r - 1], src[r], xw[r], xe[r], src[r + 1], xw[r + 1], xe[r + 1], dst[r],
+                    r, rows);
+        __syncthreads();
+        const T* above = edge_row(parity, wave, 1);      // bottom row of the wave above
+        const T* below = edge_row(parity, wave + 2, 0);  // top row of the wave below
+        T top[C], bot[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            top[c] = above[edge_pos(lane, c)];
+            bot[c] = below[edge_pos(lane, c)];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // the loads issue before the rows that do not need them
+#pragma unroll
+        for (int r = kHalf; r < R - 1; ++r)
+            box_row(src[r - 1], xw[r - 1], xe[r - 1], src[r], xw[r], xe[r], src[r + 1], xw[r + 1], xe[r + 1], dst[r],
+                    r, rows);
+        const T tw = wave_shr1_or(halo_w<HALO_ROWS>(q0 - 1), top[C - 1]);
+        const T te = wave_shl1_or(halo_e<HALO_ROWS>(q0 - 1), top[0]);
+        box_row(top, tw, te, src[0], xw[0], xe[0], src[1], xw[1], xe[1], dst[0], 0, rows);
+        const T dw = wave_shr1_or(halo_w<HALO_ROWS>(q0 + R), bot[C - 1]);
+        const T de = wave_shl1_or(halo_e<HALO_ROWS>(q0 + R), bot[0]);
+        box_row(src[R - 2], xw[R - 2], xe[R - 2], src[R - 1], xw[R - 1], xe[R - 1], bot, dw, de, dst[R - 1], R - 1,
+                rows);
+    }
+
+    // Row r of one box-stencil step: the three source rows s (r-1), m (r), n
+    // (r+1) with their west/east lane neighbours; the nine products in the
+    // weights' order (sw, s, se, w, c, e, nw, n, ne), as the oracle sums them.
+    __device__ __forceinline__ void box_row(const T (&sr)[C], T sW, T sE, const T (&mr)[C], T mW, T mE,
+                                            const T (&nr)[C], T nW, T nE, T (&out)[C], int r, int rows)
     {
         if constexpr (ROWCHECK) {
             const int g = g0 + r;
             if (g < 1 || g > rows) return;
         }
-        T hs = bw, hm = bw, hn = bw, es = be, em = be, en = be;
-        if constexpr (HALO_ROWS) {
-            const int q = wave * R + r;  // halo index of row offset r - 1
-            hs = hbw[q];
-            hm = hbw[q + 1];
-            hn = hbw[q + 2];
-            es = hbe[q];
-            em = hbe[q + 1];
-            en = hbe[q + 2];
-        }
-        T sr[C], mr[C], nr[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            sr[c] = (r == 0) ? top[c] : src[r - 1][c];
-            mr[c] = src[r][c];
-            nr[c] = (r == R - 1) ? bot[c] : src[r + 1][c];
-        }
-        const T sW = wave_shr1_or(hs, sr[C - 1]), sE = wave_shl1_or(es, sr[0]);
-        const T mW = wave_shr1_or(hm, mr[C - 1]), mE = wave_shl1_or(em, mr[0]);
-        const T nW = wave_shr1_or(hn, nr[C - 1]), nE = wave_shl1_or(en, nr[0]);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const T a[9] = {c == 0 ? sW : sr[c - 1], sr[c], c == C - 1 ? sE : sr[c + 1],
                             c == 0 ? mW : mr[c - 1], mr[c], c == C - 1 ? mE : mr[c + 1],
                             c == 0 ? nW : nr[c - 1], nr[c], c == C - 1 ? nE : nr[c + 1]};
             T v = j2d9pt<FMA>(a, k);
-            if constexpr (COLMASK) v = colact[c] ? v : dst[r][c];
-            dst[r][c] = v;
+            if constexpr (COLMASK) v = colact[c] ? v : out[c];
+            out[c] = v;
         }
-        if constexpr (HALO_ROWS) __builtin_amdgcn_sched_barrier(0);
-        if constexpr (sizeof(T) == 4 && R > 16) {
+        if constexpr (sizeof(T) == 4 && R > 8) {
             if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
     }

@@ -25,7 +25,9 @@ STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID_ARG", -2: "DTB_ERR_UNSUPPORTED", -3:
           -4: "DTB_ERR_OUT_OF_MEMORY", -5: "DTB_ERR_HIP", -6: "DTB_ERR_TIMEOUT", -7: "DTB_ERR_NOT_PLANNED",
           -8: "DTB_ERR_MISMATCH"}
 DESCRIBE_FIELDS = ("path", "workgroups", "ghost_k", "depth_D", "ext_rows", "ext_cols", "tiles_rows",
-                   "tiles_cols", "rows_per_lane", "cols_per_lane", "big_tiles", "exact", "waves", "sync")
+                   "tiles_cols", "rows_per_lane", "cols_per_lane", "big_tiles", "exact", "waves", "sync",
+                   "stencil")
+STENCIL_J2D5PT, STENCIL_BOX = 5, 9
 TEST_MAX_NEIGHBOURS = 24
 TIMING_SLOTS = 11
 TEST_LAYOUT_STRIDE = 8 + TEST_MAX_NEIGHBOURS
@@ -46,7 +48,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("ghost_k", ctypes.c_int32), ("depth_D", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("max_wg", ctypes.c_int32), ("exact", ctypes.c_int32),
                 ("debug_flags", ctypes.c_int32), ("tune", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("sync", ctypes.c_int32)]
+                ("sync", ctypes.c_int32), ("stencil", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -125,11 +127,12 @@ def _check(rc: int, what: str):
         raise DtbError(rc, what)
 
 
-def _coeffs(coeffs):
+def _coeffs(coeffs, n: int = 5):
     c = [float(x) for x in coeffs]
-    if len(c) != 5:
-        raise ValueError("five coefficients (c, n, s, e, w) are required")
-    return (ctypes.c_double * 5)(*c)
+    if len(c) != n:
+        raise ValueError("five coefficients (c, n, s, e, w) are required" if n == 5 else
+                         "nine coefficients (sw, s, se, w, c, e, nw, n, ne) are required")
+    return (ctypes.c_double * n)(*c)
 
 
 def _dtype_of(t) -> int:
@@ -166,18 +169,21 @@ class Plan:
 
     def __init__(self, rows: int, cols: int, pitch: int, dtype: int, T_hint: int = 0, path: int = PATH_AUTO,
                  ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0, exact: bool = False,
-                 tune: bool = False, debug: int = 0, waves: int = 0, sync: int = 0):
+                 tune: bool = False, debug: int = 0, waves: int = 0, sync: int = 0, stencil: int = 5):
         lib = load()
         self._h = ctypes.c_void_p()
         opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, debug, 1 if tune else 0,
-                        waves, sync)
+                        waves, sync, stencil)
         _check(lib.dtb_plan(ctypes.byref(self._h), rows, cols, pitch, dtype, T_hint, ctypes.byref(opts)), "dtb_plan")
         self.rows, self.cols, self.pitch, self.dtype = rows, cols, pitch, dtype
+        self.stencil = 9 if stencil == 9 else 5
 
     def run(self, grid, coeffs, T: int, stream=None, cols=None):
+        """Advance `grid` T steps in place: five coefficients (c, n, s, e, w), or nine (sw, s, se, w, c, e, nw,
+        n, ne) for a plan made with stencil=9."""
         g = _grid(grid, cols)
-        _check(load().dtb_run_plan(self._h, ctypes.byref(g), _coeffs(coeffs), int(T), _stream(stream)),
-               "dtb_run_plan")
+        _check(load().dtb_run_plan(self._h, ctypes.byref(g), _coeffs(coeffs, self.stencil), int(T),
+                                   _stream(stream)), "dtb_run_plan")
 
     def check(self, stream=None):
         _check(load().dtb_plan_check(self._h, _stream(stream)), "dtb_plan_check")

@@ -141,7 +141,7 @@ WORKLOADS = {
         _mk("j2d9pt_256x256_f64_T16", 256, 256, 16, "f64", "dirichlet", 0.25, 6,
             "3 x 3 box, small case: every tile and a ragged edge"),
         _mk("j2d9pt_2048x2048_f64_T10000", 2048, 2048, 10000, "f64", "dirichlet", 0.0, 7,
-            "3 x 3 box, whole grid resident on chip"),
+            "3 x 3 box, two big tiles (its register tiles are smaller than j2d5pt's)"),
         _mk("j2d9pt_8192x8192_f64_T1000", 8192, 8192, 1000, "f64", "dirichlet", 1.0, 8,
             "3 x 3 box, larger than on-chip memory: tile-serial sweep"),
         _mk("j2d9pt_8192x8192_f32_T1000", 8192, 8192, 1000, "f32", "dirichlet", 1.0, 8,

@@ -125,3 +125,33 @@ def test_plan_rejects_bad_sync_and_overlapped_options():
         for k, v in fields.items():
             setattr(o, k, v)
         assert _plan_rc(64, 64, 66, 0, o) == -2, fields
+
+
+def test_plan_box_stencil_options_checked_on_the_host():
+    """stencil must be 0, 5 or 9; the box has no overlapped path, no half-height or grid-barrier variant, and
+    only its own register tiles (FP64 8 rows per lane, FP32 16)."""
+    for bad in (1, 7, 25, -5):
+        o = dtb.PlanOpts()
+        o.stencil = bad
+        assert _plan_rc(64, 64, 66, 0, o) == -1, bad
+    cases = [(dtb.F64, dict(path=dtb.PATH_OVERLAPPED)),
+             (dtb.F64, dict(waves=4)),
+             (dtb.F64, dict(sync=1)),
+             (dtb.F64, dict(rows_per_lane=12)),     # the 5-point FP64 tile, not a box tile
+             (dtb.F64, dict(rows_per_lane=16)),     # the FP32 box height
+             (dtb.F32, dict(rows_per_lane=8)),      # the FP64 box height
+             (dtb.F32, dict(rows_per_lane=24, path=dtb.PATH_SWEEP))]
+    for dtype, fields in cases:
+        o = dtb.PlanOpts()
+        o.stencil = 9
+        for k, v in fields.items():
+            setattr(o, k, v)
+        assert _plan_rc(64, 64, 66, dtype, o) == -2, (dtype, fields)
+
+
+def test_box_plan_takes_nine_coefficients():
+    with pytest.raises(ValueError):
+        dtb._coeffs([0.2] * 5, 9)
+    with pytest.raises(ValueError):
+        dtb._coeffs([0.1] * 9, 5)
+    assert len(dtb._coeffs([0.1] * 9, 9)) == 9
