@@ -6,7 +6,8 @@ import this package.  The GPU library never calls it and shares no code with it.
 ``liboracle.so`` holds the plain C loops of ``j2d5pt_oracle.c`` (Listing 1 of
 the paper, repeated T times as Section 3.1 and Figure 1 describe) and
 ``j2d9pt_oracle.c`` (the 3 x 3 box, the next shape of the same method; its
-weight order and summation order are that file's stated reading).  This module
+weight order and summation order are that file's stated reading) and
+``j3d7pt_oracle.c`` (the 3-D seven-point stencil, likewise).  This module
 only loads them and marshals numpy arrays; it holds no stencil arithmetic of
 its own.  ``liboracle.so`` is compiled by ``__graft_entry__.build()`` (gcc,
 ``-O2 -fopenmp -ffp-contract=off``); ``build_if_missing()`` repeats that
@@ -16,6 +17,8 @@ Array convention (same as the C file): a 2-D array of shape
 (rows + 2, pitch), row-major, interior ``[1:rows+1, 1:cols+1]``, one-cell
 Dirichlet halo around it.  j2d5pt coefficients are ordered (c, n, s, e, w);
 j2d9pt coefficients (sw, s, se, w, c, e, nw, n, ne), S = row i-1, N = row i+1.
+j3d7pt grids are 3-D arrays of shape (depth + 2, rows + 2, pitch) (plane z,
+row i, column j), coefficients (c, n, s, e, w, t, b), T = plane z+1, B = z-1.
 """
 from __future__ import annotations
 
@@ -29,10 +32,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "j2d5pt_oracle.c")
 SRC9_PATH = os.path.join(_HERE, "j2d9pt_oracle.c")
+SRC3D_PATH = os.path.join(_HERE, "j3d7pt_oracle.c")
 
 # The one compile line for the oracle (also used by __graft_entry__.build()).
 GCC_CMD = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-std=c11", SRC_PATH, SRC9_PATH, "-o", LIB_PATH]
+           "-fno-fast-math", "-std=c11", SRC_PATH, SRC9_PATH, SRC3D_PATH, "-o", LIB_PATH]
 
 _lib = None
 
@@ -55,6 +59,12 @@ def _load():
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.POINTER(ptr_t), ctypes.c_int64, ctypes.c_int64,
                            ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                           ctypes.c_int64, ctypes.c_int]
+        for name, ptr_t in (("oracle_j3d7pt_f64", ctypes.c_double), ("oracle_j3d7pt_f32", ctypes.c_float)):
+            fn = getattr(lib, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [ctypes.POINTER(ptr_t), ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                           ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                            ctypes.c_int64, ctypes.c_int]
         lib.oracle_default_threads.restype = ctypes.c_int
         lib.oracle_default_threads.argtypes = []
@@ -108,6 +118,32 @@ def j2d9pt_f32(u: np.ndarray, coeffs, T: int, nthreads: int = 0, cols: int | Non
     rows = u.shape[0] - 2
     cols = u.shape[1] - 2 if cols is None else cols
     return _run(u, rows, cols, coeffs, T, nthreads, np.float32, "oracle_j2d9pt_f32", ctypes.c_float)
+
+
+def _run3(u: np.ndarray, coeffs, T: int, nthreads: int, cols, dtype, name: str, ctype) -> np.ndarray:
+    if u.dtype != dtype or u.ndim != 3:
+        raise TypeError(f"expected a 3-D {np.dtype(dtype).name} array")
+    depth, rows = u.shape[0] - 2, u.shape[1] - 2
+    cols = u.shape[2] - 2 if cols is None else cols
+    out = np.ascontiguousarray(u).copy()
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64).reshape(7))
+    pitch = out.shape[2]
+    rc = getattr(_load(), name)(out.ctypes.data_as(ctypes.POINTER(ctype)), depth, rows, cols, pitch,
+                                out.shape[1] * pitch, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                int(T), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"{name} returned {rc}")
+    return out
+
+
+def j3d7pt_f64(u: np.ndarray, coeffs, T: int, nthreads: int = 0, cols: int | None = None) -> np.ndarray:
+    """The 3-D seven-point stencil: u (depth+2, rows+2, pitch) advanced T steps in FP64 (a new array)."""
+    return _run3(u, coeffs, T, nthreads, cols, np.float64, "oracle_j3d7pt_f64", ctypes.c_double)
+
+
+def j3d7pt_f32(u: np.ndarray, coeffs, T: int, nthreads: int = 0, cols: int | None = None) -> np.ndarray:
+    """The 3-D seven-point stencil with every operation in FP32 (coefficients rounded to float)."""
+    return _run3(u, coeffs, T, nthreads, cols, np.float32, "oracle_j3d7pt_f32", ctypes.c_float)
 
 
 def rel_max_err(got: np.ndarray, ref: np.ndarray, rows: int | None = None, cols: int | None = None) -> float:

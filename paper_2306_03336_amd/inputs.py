@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for the j2d5pt and j2d9pt workloads.
+"""Seeded synthetic inputs for the j2d5pt, j2d9pt and j3d7pt workloads.
 
 This module only draws numbers and lays them out; it holds none of the
 stencil's arithmetic.  Both the GPU tests/benchmark and the CPU oracle take
@@ -9,7 +9,12 @@ Layout: a 2-D array of shape (rows + 2, pitch), row-major.  The interior is
 columns beyond ``cols + 1`` (pitch padding) are zero and never read.
 
 Coefficient order: j2d5pt (c, n, s, e, w); j2d9pt, the 3 x 3 box, (sw, s, se,
-w, c, e, nw, n, ne) -- rows i-1, i, i+1, each west to east.
+w, c, e, nw, n, ne) -- rows i-1, i, i+1, each west to east; j3d7pt (c, n, s,
+e, w, t, b) -- t for plane z+1, b for plane z-1.
+
+3-D layout (j3d7pt): an array of shape (depth + 2, rows + 2, pitch), plane z,
+row i, column j; interior ``[1:depth+1, 1:rows+1, 1:cols+1]``; the one-cell
+shell around it is the Dirichlet halo.
 
 Recipes (all with ``numpy.random.default_rng``, PCG64):
 
@@ -19,6 +24,9 @@ Recipes (all with ``numpy.random.default_rng``, PCG64):
   weights summing to 1 (up to the rounding of the draw), used as drawn.
 * ``box_weights(seed)``: ``rng.dirichlet(ones(9))`` -- the same for the nine
   weights of the box.
+* ``weights7(seed)``: ``rng.dirichlet(ones(7))`` -- the seven of j3d7pt.
+* ``uniform_grid3(depth, rows, cols, seed, halo)``: interior ~ U[0, 1) drawn
+  as ``rng.random((depth, rows, cols))``; halo shell set to ``halo``.
 * ``workload(name)``: the named configurations below draw, from
   ``default_rng(seed)``, first the weights (when they are random) and then the
   interior.
@@ -72,6 +80,48 @@ def sine_grid(rows: int, cols: int, p: int = 1, q: int = 1, halo: float = 0.0,
     j = np.arange(1, cols + 1, dtype=np.float64)[None, :]
     g[1:rows + 1, 1:cols + 1] = np.sin(math.pi * p * i / (rows + 1)) * np.sin(math.pi * q * j / (cols + 1))
     return g.astype(dtype, copy=False)
+
+
+def empty_grid3(depth: int, rows: int, cols: int, halo: float = 0.0, pitch: int | None = None,
+                dtype=np.float64) -> np.ndarray:
+    """A 3-D grid whose interior is zero and whose halo shell is ``halo``."""
+    if depth < 1 or rows < 1 or cols < 1:
+        raise ValueError("depth, rows and cols must be >= 1")
+    pitch = cols + 2 if pitch is None else int(pitch)
+    if pitch < cols + 2:
+        raise ValueError("pitch must be >= cols + 2")
+    g = np.zeros((depth + 2, rows + 2, pitch), dtype=dtype)
+    g[:, :, :cols + 2] = halo
+    g[1:depth + 1, 1:rows + 1, 1:cols + 1] = 0
+    return g
+
+
+def uniform_grid3(depth: int, rows: int, cols: int, seed, halo: float = 0.0, pitch: int | None = None,
+                  dtype=np.float64) -> np.ndarray:
+    """Interior ~ U[0, 1) from ``default_rng(seed)``, drawn in FP64 plane by plane."""
+    rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)
+    g = empty_grid3(depth, rows, cols, halo, pitch, np.float64)
+    g[1:depth + 1, 1:rows + 1, 1:cols + 1] = rng.random((depth, rows, cols))
+    return g.astype(dtype, copy=False)
+
+
+def sine_grid3(depth: int, rows: int, cols: int, r: int = 1, p: int = 1, q: int = 1,
+               pitch: int | None = None, dtype=np.float64) -> np.ndarray:
+    """Interior sin(pi r z/(depth+1)) sin(pi p i/(rows+1)) sin(pi q j/(cols+1)), counted from 1; zero halo."""
+    g = empty_grid3(depth, rows, cols, 0.0, pitch, np.float64)
+    z = np.arange(1, depth + 1, dtype=np.float64)[:, None, None]
+    i = np.arange(1, rows + 1, dtype=np.float64)[None, :, None]
+    j = np.arange(1, cols + 1, dtype=np.float64)[None, None, :]
+    g[1:depth + 1, 1:rows + 1, 1:cols + 1] = (np.sin(math.pi * r * z / (depth + 1)) *
+                                              np.sin(math.pi * p * i / (rows + 1)) *
+                                              np.sin(math.pi * q * j / (cols + 1)))
+    return g.astype(dtype, copy=False)
+
+
+def weights7(seed) -> tuple:
+    rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)
+    w = rng.dirichlet(np.ones(7))
+    return tuple(float(x) for x in w)
 
 
 def dirichlet_weights(seed) -> tuple:
