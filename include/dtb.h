@@ -70,10 +70,12 @@ typedef enum {
     DTB_PATH_STEP = 1,     /* the untiled baseline: one kernel launch per time step, HBM to HBM */
     DTB_PATH_RESIDENT = 2, /* deep temporal blocking, whole grid held on chip for all T steps */
     DTB_PATH_SWEEP = 3,    /* deep temporal blocking, big tiles processed one after another (tile-serial) */
-    DTB_PATH_OVERLAPPED = 4 /* overlapped per-workgroup blocking (Section 2's "overlapped tiling within
+    DTB_PATH_OVERLAPPED = 4, /* overlapped per-workgroup blocking (Section 2's "overlapped tiling within
                                thread blocks"): one launch per depth_D steps, each workgroup loads its tile
                                with a depth_D-deep ring from HBM, advances it depth_D steps with no
                                synchronisation between workgroups and stores its owned cells; for comparison */
+    DTB_PATH_STREAM3D = 5  /* j3d7pt (dtb_plan3d): 2.5D streaming with temporal blocking, ghost_k steps per
+                              launch (see dtb_plan3d) */
 } dtb_path;
 
 /* A grid in device memory (see the storage description above). */
@@ -107,8 +109,22 @@ typedef struct {
                             device-wide barrier (the grid-level barrier of Section 3.2; for comparison) */
     int32_t stencil;     /* 0 or 5: j2d5pt (five coefficients); 9: the 3 x 3 box (nine coefficients, see
                             above): step, resident and sweep paths, 8 waves, neighbour flags; register
-                            tiles FP64 4 x 8 and FP32 4 x 16 per lane (rows_per_lane 8 / 16) */
+                            tiles FP64 4 x 8 and FP32 4 x 16 per lane (rows_per_lane 8 / 16); 7: j3d7pt,
+                            dtb_plan3d only */
 } dtb_plan_opts;
+
+/* A 3-D grid in device memory (dtb_plan3d): (depth + 2) planes of plane_pitch elements, each plane
+   (rows + 2) lines of pitch elements; interior planes 1..depth, rows 1..rows, columns 1..cols; the one-cell
+   shell around the interior is a fixed Dirichlet halo, read but never written (its edges and corners are
+   never read). */
+typedef struct {
+    void* data;          /* device pointer to cell (0, 0, 0); caller-owned */
+    int64_t depth;       /* interior planes >= 1 */
+    int64_t rows;        /* interior rows >= 1 */
+    int64_t cols;        /* interior columns >= 1 */
+    int64_t pitch;       /* elements per row, >= cols + 2 */
+    int64_t plane_pitch; /* elements per plane, >= (rows + 2) * pitch */
+} dtb_grid3d;
 
 /* Debug bits for dtb_plan_opts.debug_flags. */
 #define DTB_DEBUG_TINY_SPIN 1 /* bounded in-kernel waits give up after a few polls: exercises the
@@ -254,6 +270,41 @@ dtb_status dtb_plan_describe(dtb_plan_t plan, int64_t* values, int32_t n);
 #define DTB_NOALLOC_SCRATCH_BYTES (40960u + 1048576u + 256u + 2u * DTB_NOALLOC_MAX_BUFFER_BYTES)
 dtb_status dtb_run_noalloc(const dtb_grid* grid, const double coeffs[5], int64_t T, dtb_dtype dtype,
                            int32_t* err_flag, void* stream);
+
+/*
+ * The 3-D seven-point stencil j3d7pt -- Listing 1's update with the two
+ * neighbours of the third axis, repeated T times (Section 3.1, Figure 1); the
+ * 2.5D tiling of 3-D stencils is among the designs of Section 2:
+ *   u'[z][i][j] = w*u[z][i][j-1] + e*u[z][i][j+1] + s*u[z][i-1][j] + c*u[z][i][j]
+ *               + n*u[z][i+1][j] + b*u[z-1][i][j] + t*u[z+1][i][j],
+ * products summed in that order (fused multiply-adds by default, separately
+ * rounded products with exact = 1); coefficients passed as (c, n, s, e, w, t, b).
+ *
+ * dtb_plan3d: plan for 3-D grids of this shape and precision and allocate the
+ * workspace (a second grid buffer, the tile table).  Paths: DTB_PATH_AUTO or
+ * DTB_PATH_STREAM3D -- 2.5D streaming: each workgroup owns an (x, y) column
+ * tile over a block of depth_D planes, streams it plane by plane and advances
+ * it ghost_k (1 .. 3, default 3) steps per launch through a register pipeline
+ * of time levels, with a ghost_k-deep ring of redundant cells in every axis
+ * and no synchronisation between workgroups -- or DTB_PATH_STEP (one launch per
+ * step, HBM to HBM).  Options other than path, ghost_k, depth_D (0 = chosen by
+ * the planner), rows_per_lane (0 or the instance's: FP64 2 x 4 and FP32 4 x 4
+ * cells per lane and plane), max_wg, exact and stencil (0 or 7) must be 0:
+ * DTB_ERR_UNSUPPORTED.  Invalid shapes: DTB_ERR_INVALID_ARG, before any HIP
+ * call.  Allocates; describe() reports big_tiles = z-blocks and stencil = 7.
+ */
+dtb_status dtb_plan3d(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t cols, int64_t pitch,
+                      int64_t plane_pitch, dtb_dtype dtype, const dtb_plan_opts* opts);
+
+/*
+ * Advance a 3-D grid by T steps in place with a plan from dtb_plan3d; coeffs:
+ * seven doubles (c, n, s, e, w, t, b).  The grid's shape must match the plan
+ * (DTB_ERR_MISMATCH; also for a 2-D plan).  Ordering as dtb_run_plan (one run
+ * at a time per plan; a run on another stream waits for the previous run).
+ * Does not allocate.
+ */
+dtb_status dtb_run3d_plan(dtb_plan_t plan, const dtb_grid3d* grid, const double* coeffs, int64_t T,
+                          void* stream);
 
 /* Release a plan and its workspace (after its work has completed).  NULL is a no-op. */
 void dtb_plan_destroy(dtb_plan_t plan);

@@ -31,7 +31,7 @@ _HIP = ["-x", "hip", f"--offload-arch={ARCH}"]
 # Largest translation units first so the parallel build finishes sooner.
 SOURCES = [(f"dtb_inst_{n}.hip", _HIP) for n in ("f32_r28", "f32_r24", "batch", "f64_r24", "f64c4_r12", "f64w4_r24", "f32_r16",
                                                  "f64_r16", "f32_r8", "f64_r8", "box_f64_r8",
-                                                 "box_f32_r16")] + [
+                                                 "box_f32_r16", "3d")] + [
     ("dtb_kernels.hip", _HIP),
     ("dtb_probe.hip", _HIP),
     ("dtb_noalloc.hip", _HIP),

@@ -68,6 +68,11 @@ struct dtb_plan_s {
     SweepPlan sweep;
     // overlapped per-workgroup blocking (layout with k = D, ws as its second buffer)
     int ovl_D = 0;
+    // j3d7pt (dtb_plan3d): 2.5D streaming, K steps per launch over ntiles3 (x, y) tiles x nzb z-blocks
+    bool is3d = false;
+    int64_t depth = 0, plane_pitch = 0;
+    int K3 = 0, zb = 0, nzb = 0, ntiles3 = 0, ty3 = 0, tx3 = 0, R3 = 0, C3 = 0;
+    Tile3Desc* d_tiles3 = nullptr;
     bool grid_sync = false;  // resident path: device-wide barrier at every exchange
     uint32_t* d_bar = nullptr;
     int nwg_launch = 0;
@@ -90,6 +95,7 @@ struct dtb_plan_s {
         if (d_wgs) (void)hipFree(d_wgs);
         if (d_flags) (void)hipFree(d_flags);
         if (d_err) (void)hipFree(d_err);
+        if (d_tiles3) (void)hipFree(d_tiles3);
         for (void* p : xbuf)
             if (p) (void)hipFree(p);
     }
@@ -111,9 +117,9 @@ dtb_status check_shape(int64_t rows, int64_t cols, int64_t pitch, int dtype)
 dtb_status check_opts(const dtb_plan_opts* o)
 {
     if (!o) return DTB_OK;
-    if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_OVERLAPPED) return DTB_ERR_INVALID_ARG;
+    if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_STREAM3D) return DTB_ERR_INVALID_ARG;
     if (o->sync != 0 && o->sync != 1) return DTB_ERR_INVALID_ARG;
-    if (o->stencil != 0 && o->stencil != 5 && o->stencil != 9) return DTB_ERR_INVALID_ARG;
+    if (o->stencil != 0 && o->stencil != 5 && o->stencil != 7 && o->stencil != 9) return DTB_ERR_INVALID_ARG;
     if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0) return DTB_ERR_INVALID_ARG;
     if (o->waves != 0 && o->waves != 4 && o->waves != 8) return DTB_ERR_INVALID_ARG;
     if (o->exact != 0 && o->exact != 1) return DTB_ERR_INVALID_ARG;
@@ -131,6 +137,7 @@ int stencil_points(const dtb_plan_opts& o) { return o.stencil == 9 ? 9 : 5; }
 // waves, resident and sweep paths, neighbour flags.  Checked before any HIP call.
 dtb_status check_instance(const dtb_plan_opts& o, int dtype)
 {
+    if (o.stencil == 7 || o.path == DTB_PATH_STREAM3D) return DTB_ERR_UNSUPPORTED;  // 3-D: dtb_plan3d
     const int pts = stencil_points(o);
     if (pts == 9 && (o.path == DTB_PATH_OVERLAPPED || o.waves == 4 || o.sync == 1)) return DTB_ERR_UNSUPPORTED;
     if (o.path == DTB_PATH_STEP) return DTB_OK;
@@ -839,7 +846,7 @@ dtb_status run_plan_impl(dtb_plan_t p, const dtb_grid* g, const double* coeffs, 
 {
     if (!p || !g || !coeffs || !g->data) return DTB_ERR_INVALID_ARG;
     if (T < 0) return DTB_ERR_INVALID_ARG;
-    if (g->rows != p->rows || g->cols != p->cols || g->pitch != p->pitch) return DTB_ERR_MISMATCH;
+    if (p->is3d || g->rows != p->rows || g->cols != p->cols || g->pitch != p->pitch) return DTB_ERR_MISMATCH;
     if (T == 0) return DTB_OK;
     hipStream_t st = (hipStream_t)stream;
     if (dtb_status rc = order_after_last_run(p->done, p->has_run, p->last_stream, st); rc != DTB_OK) return rc;
@@ -1077,9 +1084,192 @@ dtb_status run_batched_impl(const dtb_problem* problems, int32_t count, hipStrea
     return DTB_OK;
 }
 
+// ---- j3d7pt: 2.5D streaming
+
+dtb_status check_shape3(int64_t depth, int64_t rows, int64_t cols, int64_t pitch, int64_t plane_pitch, int dtype)
+{
+    if (depth < 1 || rows < 1 || cols < 1 || pitch < cols + 2 || plane_pitch < (rows + 2) * pitch)
+        return DTB_ERR_INVALID_ARG;
+    if (dtype != DTB_F64 && dtype != DTB_F32) return DTB_ERR_INVALID_ARG;
+    if (depth > (1 << 30) || rows > (1 << 30) || cols > (1 << 30)) return DTB_ERR_UNSUPPORTED;
+    return DTB_OK;
+}
+
+dtb_status plan3d_impl(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t cols, int64_t pitch,
+                       int64_t plane_pitch, int dtype, const dtb_plan_opts* opts)
+{
+    if (!out) return DTB_ERR_INVALID_ARG;
+    *out = nullptr;
+    dtb_status st = check_shape3(depth, rows, cols, pitch, plane_pitch, dtype);
+    if (st != DTB_OK) return st;
+    st = check_opts(opts);
+    if (st != DTB_OK) return st;
+    dtb_plan_opts o{};
+    if (opts) o = *opts;
+    if (o.stencil != 0 && o.stencil != 7) return DTB_ERR_INVALID_ARG;
+    // The streaming path: K = 1 .. 3 steps per launch, 8 waves, neighbour-free (overlapped) tiles.
+    if (o.path != DTB_PATH_AUTO && o.path != DTB_PATH_STEP && o.path != DTB_PATH_STREAM3D) return DTB_ERR_UNSUPPORTED;
+    if (o.ghost_k > 3 || o.sync != 0 || o.tune != 0 || (o.waves != 0 && o.waves != 8) ||
+        (o.debug_flags & ~DTB_DEBUG_TINY_SPIN) != 0)
+        return DTB_ERR_UNSUPPORTED;
+    const bool fma = o.exact == 0;
+    const int path = o.path == DTB_PATH_STEP ? DTB_PATH_STEP : DTB_PATH_STREAM3D;
+    int C = 0, R = 0;
+    const int K = o.ghost_k > 0 ? o.ghost_k : 3;
+    if (path == DTB_PATH_STREAM3D) {
+        if (!dtb_stream3d_kernel(dtype, K, fma, &C, &R)) return DTB_ERR_UNSUPPORTED;
+        if (o.rows_per_lane != 0 && o.rows_per_lane != R) return DTB_ERR_UNSUPPORTED;
+    }
+    DeviceInfo di;
+    if (!device_info(&di)) return DTB_ERR_HIP;
+    std::unique_ptr<dtb_plan_s> p(new dtb_plan_s());
+    p->device = di.device;
+    p->is3d = true;
+    p->depth = depth;
+    p->rows = rows;
+    p->cols = cols;
+    p->pitch = pitch;
+    p->plane_pitch = plane_pitch;
+    p->dtype = dtype;
+    p->pts = 7;
+    p->fma = fma;
+    p->path = path;
+    p->debug = o.debug_flags;
+    const size_t bytes = (size_t)(depth + 2) * (size_t)plane_pitch * elem_size(dtype);
+    if (path == DTB_PATH_STREAM3D) {
+        std::vector<Span3> ys, xs;
+        const int ER = kStreamWaves * R, EC = kWaveSize * C;
+        if (!split_axis3(rows, ER, K, &ys) || !split_axis3(cols, EC, K, &xs)) return DTB_ERR_UNSUPPORTED;
+        std::vector<Tile3Desc> tiles;
+        for (const Span3& y : ys)
+            for (const Span3& x : xs) {
+                Tile3Desc t{};
+                t.ext_r0 = y.e0;
+                t.ext_c0 = x.e0;
+                t.own_r0 = y.own0;
+                t.own_r1 = y.own1;
+                t.own_c0 = x.own0;
+                t.own_c1 = x.own1;
+                t.edge = (y.e0 < 1 || y.e0 + ER - 1 > rows || x.e0 < 1 || x.e0 + EC - 1 > cols) ? 1 : 0;
+                tiles.push_back(t);
+            }
+        const int ntiles = (int)tiles.size();
+        int zb = 0;
+        if (o.depth_D > 0) {
+            zb = (int)std::min<int64_t>(o.depth_D, depth);
+        } else {
+            // The block height with the least modelled launch time: taller blocks amortise the K-deep z ring,
+            // more blocks fill the compute units.  Measured: a launch streams best with several waves of
+            // workgroups queued per compute unit (512^3: 16-32 planes per block, 1600-3200 workgroups, beat
+            // 128-257 planes by 1.06-1.3x in FP64 and FP32), so blocks that leave fewer than four workgroups
+            // per compute unit are taken only when the grid is too shallow for more.
+            double best = 1e300;
+            const int cap = o.max_wg > 0 ? std::min(o.max_wg, di.n_cu) : di.n_cu;
+            const int64_t want = 4 * (int64_t)cap;
+            const bool deep_enough = (int64_t)ntiles * ((depth + 4 * K - 1) / (4 * K)) >= want;
+            for (int z = 1; z <= depth; z = z < 16 ? z + 1 : z + z / 8) {
+                const int nz = (int)((depth + z - 1) / z);
+                const int64_t nwg = (int64_t)ntiles * nz;
+                if (nwg > INT32_MAX / 2) continue;
+                if (deep_enough && (nwg < want || z < 4 * K)) continue;
+                const double t = stream3_launch_us((int)nwg, cap, ER, EC, z, K, (int)elem_size(dtype), depth,
+                                                   depth * rows * cols);
+                if (t < best) {
+                    best = t;
+                    zb = z;
+                }
+            }
+        }
+        const int64_t nzb = (depth + zb - 1) / zb;
+        if ((int64_t)ntiles * nzb > INT32_MAX / 2) return DTB_ERR_UNSUPPORTED;
+        p->K3 = K;
+        p->zb = zb;
+        p->nzb = (int)nzb;
+        p->ntiles3 = ntiles;
+        p->ty3 = (int)ys.size();
+        p->tx3 = (int)xs.size();
+        p->R3 = R;
+        p->C3 = C;
+        if (hipMalloc(&p->d_tiles3, tiles.size() * sizeof(Tile3Desc)) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+        if (hipMemcpy(p->d_tiles3, tiles.data(), tiles.size() * sizeof(Tile3Desc), hipMemcpyHostToDevice) != hipSuccess)
+            return DTB_ERR_HIP;
+    }
+    if (hipMalloc(&p->ws, bytes) != hipSuccess) return DTB_ERR_OUT_OF_MEMORY;
+    if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) return DTB_ERR_HIP;
+    *out = p.release();
+    return DTB_OK;
+}
+
+dtb_status run3d_impl(dtb_plan_t p, const dtb_grid3d* g, const double* coeffs, int64_t T, void* stream)
+{
+    if (!p || !g || !coeffs || !g->data || T < 0) return DTB_ERR_INVALID_ARG;
+    if (!p->is3d || g->depth != p->depth || g->rows != p->rows || g->cols != p->cols || g->pitch != p->pitch ||
+        g->plane_pitch != p->plane_pitch)
+        return DTB_ERR_MISMATCH;
+    if (T == 0) return DTB_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtb_status rc = order_after_last_run(p->done, p->has_run, p->last_stream, st); rc != DTB_OK) return rc;
+    const int depth = (int)p->depth, rows = (int)p->rows, cols = (int)p->cols;
+    if (launch_copy_shell3d(p->dtype, g->data, p->ws, p->pitch, p->plane_pitch, depth, rows, cols, st) != hipSuccess)
+        return DTB_ERR_HIP;
+    void* bufs[2] = {g->data, p->ws};
+    int64_t done = 0, rounds = 0;
+    if (p->path == DTB_PATH_STEP) {
+        for (; done < T; ++done, ++rounds)
+            if (launch_step3d(p->dtype, p->fma, bufs[rounds & 1], bufs[(rounds + 1) & 1], p->pitch, p->plane_pitch,
+                              depth, rows, cols, coeffs, st) != hipSuccess)
+                return DTB_ERR_HIP;
+    } else {
+        Stream3Args A{};
+        A.pitch = p->pitch;
+        A.plane_pitch = p->plane_pitch;
+        A.depth = depth;
+        A.rows = rows;
+        A.cols = cols;
+        A.zb = p->zb;
+        A.nzb = p->nzb;
+        A.ntiles = p->ntiles3;
+        for (int i = 0; i < 7; ++i) A.coeffs[i] = coeffs[i];
+        const Tile3Desc* tiles = p->d_tiles3;
+        const dim3 grid((unsigned)((int64_t)p->ntiles3 * p->nzb)), block(kStreamWaves * kWaveSize);
+        for (; done < T; ++rounds) {
+            // The last launch may take fewer steps: the K-step layout serves it (a deeper ring than needed).
+            const int k = (int)std::min<int64_t>(p->K3, T - done);
+            int C = 0, R = 0;
+            const void* f = dtb_stream3d_kernel(p->dtype, k, p->fma, &C, &R);
+            if (!f) return DTB_ERR_UNSUPPORTED;
+            A.src = bufs[rounds & 1];
+            A.dst = bufs[(rounds + 1) & 1];
+            void* args[] = {&A, (void*)&tiles};
+            if (hipLaunchKernel(f, grid, block, args, 0, st) != hipSuccess) return DTB_ERR_HIP;
+            done += k;
+        }
+    }
+    if (rounds & 1) {
+        if (launch_copy_interior3d(p->dtype, p->ws, g->data, p->pitch, p->plane_pitch, depth, rows, cols, st) !=
+            hipSuccess)
+            return DTB_ERR_HIP;
+    }
+    if (hipEventRecord(p->done, st) != hipSuccess) return DTB_ERR_HIP;
+    p->last_stream = st;
+    p->has_run = true;
+    return DTB_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+dtb_status dtb_plan3d(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t cols, int64_t pitch, int64_t plane_pitch,
+                      dtb_dtype dtype, const dtb_plan_opts* opts)
+{
+    return plan3d_impl(out, depth, rows, cols, pitch, plane_pitch, (int)dtype, opts);
+}
+
+dtb_status dtb_run3d_plan(dtb_plan_t plan, const dtb_grid3d* grid, const double* coeffs, int64_t T, void* stream)
+{
+    return run3d_impl(plan, grid, coeffs, T, stream);
+}
 
 dtb_status dtb_plan(dtb_plan_t* out, int64_t rows, int64_t cols, int64_t pitch, dtb_dtype dtype, int64_t T_hint,
                     const dtb_plan_opts* opts)
@@ -1188,6 +1378,14 @@ dtb_status dtb_plan_timing(dtb_plan_t p, uint64_t* out, int32_t n, void* stream)
 dtb_status dtb_plan_describe(dtb_plan_t p, int64_t* v, int32_t n)
 {
     if (!p || (n > 0 && !v) || n < 0) return DTB_ERR_INVALID_ARG;
+    if (p->is3d) {
+        const bool sm = p->path == DTB_PATH_STREAM3D;
+        const int64_t all[] = {p->path, sm ? (int64_t)p->ntiles3 * p->nzb : 0, p->K3, p->zb,
+                               sm ? kStreamWaves * p->R3 : 0, sm ? kWaveSize * p->C3 : 0, p->ty3, p->tx3, p->R3, p->C3,
+                               p->nzb, p->fma ? 0 : 1, sm ? kStreamWaves : 0, 0, p->pts};
+        for (int32_t i = 0; i < n && i < (int32_t)(sizeof(all) / sizeof(all[0])); ++i) v[i] = all[i];
+        return DTB_OK;
+    }
     const Layout& L = p->layout;
     const bool sw = p->path == DTB_PATH_SWEEP, ov = p->path == DTB_PATH_OVERLAPPED;
     const int64_t all[] = {p->path, sw ? p->nwg_launch : L.nwg, ov ? 0 : L.k, sw ? p->sweep.D : (ov ? p->ovl_D : 0), L.ER, L.EC,

@@ -118,4 +118,28 @@ struct WorkItem {
     int32_t job, local;
 };
 
+// ---- j3d7pt streaming (dtb_stream3d.h)
+
+constexpr int kStreamWaves = 8;
+
+// One workgroup's work: an (x, y) tile and a block of planes.
+struct Tile3Desc {
+    int32_t ext_r0, ext_c0;   // storage row / column of the extended tile's first row / column (may be 0: halo)
+    int32_t own_r0, own_r1;   // owned rows [own_r0, own_r1), storage coordinates
+    int32_t own_c0, own_c1;   // owned columns
+    int32_t edge;             // the extended tile holds cells outside the interior (halo or beyond the grid)
+    int32_t pad_;
+};
+
+struct Stream3Args {
+    const void* src;
+    void* dst;
+    int64_t pitch, plane_pitch;
+    int32_t depth, rows, cols;
+    int32_t zb;               // planes per z-block
+    int32_t nzb;              // z-blocks
+    int32_t ntiles;           // (x, y) tiles
+    double coeffs[7];         // c, n, s, e, w, t, b
+};
+
 }  // namespace dtb

@@ -45,6 +45,19 @@ hipError_t launch_reset_counter(uint32_t* bar, hipStream_t st);
 // FP32 4 x 8, 4 x 24).
 const void* dtb_ovl_kernel(int dtype, int R, bool fma, bool colmask, bool rowcheck, int* C, int* waves);
 
+// ---- j3d7pt (dtb_inst_3d.hip)
+
+// The K-step streaming kernel (arguments: Stream3Args, Tile3Desc table) for
+// dtype and K (1 .. 3), or nullptr; *C, *R: columns and rows per lane.
+const void* dtb_stream3d_kernel(int dtype, int K, bool fma, int* C, int* R);
+// One step of the untiled baseline (seven coefficients c, n, s, e, w, t, b).
+hipError_t launch_step3d(int dtype, bool fma, const void* in, void* out, int64_t pitch, int64_t plane_pitch,
+                         int depth, int rows, int cols, const double* coeffs, hipStream_t st);
+hipError_t launch_copy_shell3d(int dtype, const void* src, void* dst, int64_t pitch, int64_t plane_pitch, int depth,
+                               int rows, int cols, hipStream_t st);
+hipError_t launch_copy_interior3d(int dtype, const void* src, void* dst, int64_t pitch, int64_t plane_pitch,
+                                  int depth, int rows, int cols, hipStream_t st);
+
 // The batched persistent kernel (arguments: ProbDesc*, JobDesc*, WgDesc*
 // table, work-list offsets, work items, flags, error word, spin limit); the
 // register-tile instances it carries (at most kMaxBatchInsts) into insts,

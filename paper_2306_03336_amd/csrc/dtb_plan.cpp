@@ -564,4 +564,57 @@ bool plan_batch(const std::vector<BatchSpec>& probs, const std::vector<TileInst>
     return true;
 }
 
+// ---- 3-D streaming
+
+bool split_axis3(int64_t n, int E, int K, std::vector<Span3>* out)
+{
+    out->clear();
+    if (n < 1 || E < 2 * K + 1 || n > INT32_MAX / 2) return false;
+    int64_t own0 = 1, e0 = 0;
+    while (true) {
+        if (e0 + E >= n + 2) {
+            // The last range reaches the far halo (row n + 1): it owns everything up to it.  Moved back so
+            // that it ends at the halo (a deeper near ring, never a shallower one), not before storage row 0.
+            Span3 sp;
+            sp.e0 = (int)std::max<int64_t>(0, n + 2 - E);
+            sp.own0 = (int)own0;
+            sp.own1 = (int)(n + 1);
+            out->push_back(sp);
+            return true;
+        }
+        Span3 sp;
+        sp.e0 = (int)e0;
+        sp.own0 = (int)own0;
+        sp.own1 = (int)(e0 + E - K);
+        out->push_back(sp);
+        own0 = sp.own1;
+        e0 = own0 - K;
+    }
+}
+
+double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int elem_bytes, int64_t depth,
+                         int64_t interior_cells)
+{
+    // Measured on MI355X (512^3, one workgroup per compute unit): a launch streams at about 4.3 TB/s when
+    // every compute unit holds a workgroup, and each compute unit pulls its share, so fewer workgroups than
+    // compute units, or a last partial wave of them, leave bandwidth unused.  Bytes: every z-block loads its
+    // tile for its planes and a K-deep ring below and above; the owned cells are stored once.  The compute
+    // floor (a register-tile step per level per plane) rarely binds.
+    const double bw = 4.3e6;  // bytes per microsecond
+    const int64_t nz = (depth + zb - 1) / zb;
+    const int64_t tiles = nz > 0 ? nwg / nz : nwg;
+    double planes = 0;
+    for (int64_t b = 0; b < nz; ++b) {
+        const int64_t z0 = 1 + b * zb, z1 = std::min<int64_t>(z0 + zb, depth + 1);
+        planes += (double)(std::min<int64_t>(z1 + K, depth + 2) - std::max<int64_t>(z0 - K, 0));
+    }
+    const double bytes = planes * tiles * ER * EC * elem_bytes + (double)interior_cells * elem_bytes;
+    const double w = (double)nwg / std::max(1, n_cu);
+    const double mem = bytes / bw * (std::ceil(w) / w);
+    const double cell = elem_bytes == 8 ? 70e-6 : 50e-6;
+    const double compute = std::ceil(w) * (zb + 2.0 * K) * ((double)ER * EC * cell * K + 0.3);
+    return std::max(mem, compute);
+}
+
 }  // namespace dtb
+

@@ -193,6 +193,26 @@ inline uint32_t batch_spin_limit(double makespan_us, uint32_t floor)
     return polls >= 4.0e9 ? 4000000000u : (uint32_t)polls;
 }
 
+// ---- 3-D streaming (j3d7pt): overlapped tiles of one axis
+
+// One tile of an axis of `n` interior cells (storage 0 .. n+1): extended range
+// [e0, e0 + E), owned [own0, own1).
+struct Span3 {
+    int e0 = 0, own0 = 0, own1 = 0;
+};
+
+// Cover the interior 1 .. n of an axis with extended ranges of E cells whose
+// owned parts stay K cells away from every open edge (an edge at the grid's
+// halo is closed: the first range starts at the halo, the last one ends at
+// it).  Returns false if E is too short for a K-deep ring (E < 2K + 1).
+bool split_axis3(int64_t n, int E, int K, std::vector<Span3>* out);
+
+// Model time (us) of one K-step streaming launch over nwg workgroups (tiles x
+// z-blocks of zb planes) of an ER x EC tile, one workgroup per compute unit,
+// for a grid of `depth` planes and `interior_cells` cells.
+double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int elem_bytes, int64_t depth,
+                         int64_t interior_cells);
+
 // Exchange points run_epochs performs for a segment of `steps` steps.
 inline int exchanges_per_segment(int64_t steps, int k)
 {

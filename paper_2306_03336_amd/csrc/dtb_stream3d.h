@@ -1,0 +1,261 @@
+// dtb_stream3d.h -- the 3-D seven-point stencil (j3d7pt) by 2.5D streaming
+// with temporal blocking.
+//
+// The update: every interior cell of a (depth + 2) x (rows + 2) x pitch grid
+// becomes w*W + e*E + s*S + c*C + n*N + b*B + t*T of the previous step's
+// values (W/E columns j-1/j+1, S/N rows i-1/i+1, B/T planes z-1/z+1), products
+// summed in that order; the one-cell shell around the interior is a fixed
+// Dirichlet halo.  This is Listing 1's update with the two neighbours of the
+// third axis, repeated T times (Section 3.1, Figure 1); Section 2 names 2.5D
+// tiling of 3-D stencils among the related designs.
+//
+// Design.  A 3-D grid does not fit on chip, so each workgroup owns a column
+// of the grid: an (x, y) tile, ER = WAVES * R rows by EC = 64 * C columns,
+// over a block of Zb planes, and streams it plane by plane.  One launch
+// advances the grid K steps: the workgroup keeps, for every time level l =
+// 0 .. K-1, the three most recent planes of that level in registers (the
+// "2.5D" window: rows across waves, columns across lanes, planes across
+// registers), so that level l+1 of plane q is computed as soon as level l of
+// plane q+1 exists.  Level 0 is loaded from HBM (one plane ahead, so that the
+// load overlaps the compute), level K is stored.  Neighbouring workgroups do
+// not synchronise: each tile carries a K-deep ring of redundant cells in x and
+// y, and each z-block K planes below and above (overlapped, or trapezoidal,
+// blocking in all three axes; stale values from a tile's open edges move one
+// cell per level and never reach the owned cells).  Cells outside the interior
+// (the halo shell, where a tile meets the grid boundary) keep their values at
+// every level.  Within a plane, W/E neighbours come from the neighbouring lane
+// (DPP), S/N from the neighbouring row of the same lane or, at a wave's first
+// and last row, from the wave above or below through LDS: every level
+// publishes its newest plane's edge rows once per plane, and one workgroup
+// barrier per plane separates publishing from reading (two LDS buffers,
+// alternating).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dtb_internal.h"
+#include "dtb_stencil.h"
+
+namespace dtb {
+
+// Seven weights; the order of the products is W, E, S, C, N, B, T.
+template <typename T>
+struct Coef7 {
+    T c, n, s, e, w, t, b;
+};
+
+template <bool FMA, typename T>
+__device__ __forceinline__ T j3d7pt(T W, T E, T S, T Cv, T N, T B, T Tv, const Coef7<T>& k)
+{
+    T acc = k.w * W;
+    if constexpr (FMA) {
+        acc = fma_t(k.e, E, acc);
+        acc = fma_t(k.s, S, acc);
+        acc = fma_t(k.c, Cv, acc);
+        acc = fma_t(k.n, N, acc);
+        acc = fma_t(k.b, B, acc);
+        acc = fma_t(k.t, Tv, acc);
+    } else {
+        acc = acc + k.e * E;
+        acc = acc + k.s * S;
+        acc = acc + k.c * Cv;
+        acc = acc + k.n * N;
+        acc = acc + k.b * B;
+        acc = acc + k.t * Tv;
+    }
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_shr1_3(T v)  // lane l gets lane l-1's value (lane 0: 0)
+{
+    return __builtin_amdgcn_update_dpp((T)0, v, 0x138, 0xf, 0xf, true);
+}
+template <typename T>
+__device__ __forceinline__ T wave_shl1_3(T v)  // lane l gets lane l+1's value (lane 63: 0)
+{
+    return __builtin_amdgcn_update_dpp((T)0, v, 0x130, 0xf, 0xf, true);
+}
+
+template <typename T, int C, int R, int K, int WAVES>
+struct Stream3Geo {
+    static constexpr int ER = WAVES * R;
+    static constexpr int EC = 64 * C;
+    // LDS: [parity 2][level K][wave][top/bottom 2][EC]
+    static constexpr size_t kLdsBytes = (size_t)2 * K * WAVES * 2 * EC * sizeof(T);
+};
+
+// The register pipeline of one workgroup.
+template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE>
+struct Stream3 {
+    using G = Stream3Geo<T, C, R, K, WAVES>;
+    T win[K][3][R][C];   // level l's three most recent planes (slot: the plane's offset from the first, mod 3)
+    T next[R][C];        // the level-0 plane being loaded one iteration ahead
+    Coef7<T> k;
+    T* lds;
+    int wave, lane;
+    int g0;              // storage row of this wave's row 0
+    int col0;            // storage column of this lane's slot 0
+    bool rowact[R];      // EDGE: row inside the interior
+    bool colact[C];      // EDGE: column inside the interior
+
+    __device__ __forceinline__ T* edge_row(int parity, int level, int w, int bottom)
+    {
+        return lds + ((size_t)(((parity * K + level) * WAVES + w) * 2 + bottom)) * G::EC;
+    }
+
+    // Load plane z of the source (cells outside the stored grid read as 0).
+    __device__ __forceinline__ void load_plane(const T* src, const Stream3Args& A, int z, T (&dst)[R][C])
+    {
+        const T* plane = src + (int64_t)z * A.plane_pitch;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int g = g0 + r;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int col = col0 + c;
+                T v = T(0);
+                if (!EDGE || (g <= A.rows + 1 && col <= A.cols + 1)) v = plane[(int64_t)g * A.pitch + col];
+                dst[r][c] = v;
+            }
+        }
+    }
+
+    // Publish a plane's first and last rows for the waves above and below.
+    __device__ __forceinline__ void publish(int parity, int level, const T (&x)[R][C])
+    {
+        T* top = edge_row(parity, level, wave, 0);
+        T* bot = edge_row(parity, level, wave, 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            top[c * 64 + lane] = x[0][c];
+            bot[c * 64 + lane] = x[R - 1][c];
+        }
+    }
+
+    // Level `level` + 1 of plane q from level `level`'s planes q-1 (bw), q (cw), q+1 (aw): writes out.
+    // above/below: the neighbouring waves' edge rows of plane q (zeros at the tile's first / last row).
+    __device__ __forceinline__ void compute(const T (&bw)[R][C], const T (&cw)[R][C], const T (&aw)[R][C],
+                                            const T (&above)[C], const T (&below)[C], bool plane_interior,
+                                            T (&out)[R][C])
+    {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T wl = wave_shr1_3(cw[r][C - 1]);
+            const T el = wave_shl1_3(cw[r][0]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T W = c == 0 ? wl : cw[r][c - 1];
+                const T E = c == C - 1 ? el : cw[r][c + 1];
+                const T S = r == 0 ? above[c] : cw[r - 1][c];
+                const T N = r == R - 1 ? below[c] : cw[r + 1][c];
+                T v = j3d7pt<FMA>(W, E, S, cw[r][c], N, bw[r][c], aw[r][c], k);
+                if constexpr (EDGE) v = (rowact[r] && colact[c]) ? v : cw[r][c];
+                out[r][c] = plane_interior ? v : cw[r][c];
+            }
+        }
+    }
+};
+
+// Slot of plane p0 + 3m + u - l in a level's three-slot window (u, l known at compile time after unrolling).
+__host__ __device__ constexpr int stream_slot(int u, int l) { return ((u - l) % 3 + 3) % 3; }
+
+// One K-step launch of one workgroup: tile `d`, owned planes [zo0, zo1).
+template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE>
+__device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Desc& d, int zo0, int zo1, T* lds)
+{
+    Stream3<T, C, R, K, WAVES, FMA, EDGE> s;
+    s.lds = lds;
+    s.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    s.lane = threadIdx.x & 63;
+    s.g0 = d.ext_r0 + s.wave * R;
+    s.col0 = d.ext_c0 + s.lane * C;
+    s.k = Coef7<T>{(T)A.coeffs[0], (T)A.coeffs[1], (T)A.coeffs[2], (T)A.coeffs[3],
+                   (T)A.coeffs[4], (T)A.coeffs[5], (T)A.coeffs[6]};
+#pragma unroll
+    for (int r = 0; r < R; ++r) s.rowact[r] = s.g0 + r >= 1 && s.g0 + r <= A.rows;
+#pragma unroll
+    for (int c = 0; c < C; ++c) s.colact[c] = s.col0 + c >= 1 && s.col0 + c <= A.cols;
+    const T* src = (const T*)A.src;
+    T* dst = (T*)A.dst;
+    // Level 0 (loaded) covers planes [p0, p_end); level l covers [lo(l), hi(l)), one plane less on each
+    // side per level, clipped to the stored planes 0 .. depth + 1; level K is [zo0, zo1).
+    const int p0 = zo0 - K > 0 ? zo0 - K : 0;
+    const int p_end = zo1 + K < A.depth + 2 ? zo1 + K : A.depth + 2;
+    s.load_plane(src, A, p0, s.next);
+    // Iteration p: level 0 takes plane p, level l = 1 .. K produces plane p - l (when it has one); the
+    // last owned plane, zo1 - 1, leaves level K at iteration zo1 - 1 + K.
+    const int p_stop = zo1 + K;
+    for (int pb = p0; pb < p_stop; pb += 3) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int p = pb + u;
+            if (p >= p_stop) break;
+            const int par = p & 1;
+            if (p < p_end) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) s.win[0][stream_slot(u, 0)][r][c] = s.next[r][c];
+                if (p + 1 < p_end) s.load_plane(src, A, p + 1, s.next);
+            }
+            // The centre planes' edge rows were published last iteration (the other LDS buffer).
+            __syncthreads();
+#pragma unroll
+            for (int l = 1; l <= K; ++l) {
+                const int q = p - l;
+                const int lo = zo0 - K + l > 0 ? zo0 - K + l : 0;
+                const int hi = zo1 + K - l < A.depth + 2 ? zo1 + K - l : A.depth + 2;
+                if (q < lo || q >= hi) continue;
+                T above[C], below[C];
+                const T* ab = s.edge_row(par ^ 1, l - 1, s.wave > 0 ? s.wave - 1 : 0, 1);
+                const T* be = s.edge_row(par ^ 1, l - 1, s.wave < WAVES - 1 ? s.wave + 1 : 0, 0);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    above[c] = s.wave > 0 ? ab[c * 64 + s.lane] : T(0);
+                    below[c] = s.wave < WAVES - 1 ? be[c * 64 + s.lane] : T(0);
+                }
+                const bool interior = q >= 1 && q <= A.depth;
+                if (l < K) {
+                    s.compute(s.win[l - 1][stream_slot(u, l + 1)], s.win[l - 1][stream_slot(u, l)],
+                              s.win[l - 1][stream_slot(u, l - 1)], above, below, interior,
+                              s.win[l][stream_slot(u, l)]);
+                } else {
+                    T out[R][C];
+                    s.compute(s.win[l - 1][stream_slot(u, l + 1)], s.win[l - 1][stream_slot(u, l)],
+                              s.win[l - 1][stream_slot(u, l - 1)], above, below, interior, out);
+                    T* plane = dst + (int64_t)q * A.plane_pitch;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int g = s.g0 + r;
+                        if (g < d.own_r0 || g >= d.own_r1) continue;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            const int col = s.col0 + c;
+                            if (col >= d.own_c0 && col < d.own_c1) plane[(int64_t)g * A.pitch + col] = out[r][c];
+                        }
+                    }
+                }
+            }
+            // Publish every level's newest plane (the centre planes of the next iteration).
+#pragma unroll
+            for (int l = 0; l < K; ++l) s.publish(par, l, s.win[l][stream_slot(u, l)]);
+        }
+    }
+}
+
+// The K-step streaming kernel.  Workgroup b: tile b % ntiles, z-block b / ntiles.
+template <typename T, int C, int R, int K, int WAVES, bool FMA>
+__global__ __launch_bounds__(WAVES * 64, 1) void k_stream3d(Stream3Args A, const Tile3Desc* __restrict__ tiles)
+{
+    using G = Stream3Geo<T, C, R, K, WAVES>;
+    __shared__ __attribute__((aligned(16))) char lds_raw[G::kLdsBytes];
+    const Tile3Desc d = tiles[blockIdx.x % A.ntiles];
+    const int zblk = blockIdx.x / A.ntiles;
+    const int zo0 = 1 + zblk * A.zb;
+    const int zo1 = zo0 + A.zb < A.depth + 1 ? zo0 + A.zb : A.depth + 1;
+    if (d.edge) stream3_run<T, C, R, K, WAVES, FMA, true>(A, d, zo0, zo1, (T*)lds_raw);
+    else stream3_run<T, C, R, K, WAVES, FMA, false>(A, d, zo0, zo1, (T*)lds_raw);
+}
+
+}  // namespace dtb

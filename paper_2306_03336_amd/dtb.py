@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdtb.so")
 
 F64, F32 = 0, 1
 DEBUG_TINY_SPIN, DEBUG_POISON, DEBUG_TIMING, DEBUG_DIRECT_XCHG = 1, 2, 4, 8
-PATH_AUTO, PATH_STEP, PATH_RESIDENT, PATH_SWEEP, PATH_OVERLAPPED = 0, 1, 2, 3, 4
+PATH_AUTO, PATH_STEP, PATH_RESIDENT, PATH_SWEEP, PATH_OVERLAPPED, PATH_STREAM3D = 0, 1, 2, 3, 4, 5
 SYNC_NEIGHBOURS, SYNC_GRID_BARRIER = 0, 1
 STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID_ARG", -2: "DTB_ERR_UNSUPPORTED", -3: "DTB_ERR_NOT_CORESIDENT",
           -4: "DTB_ERR_OUT_OF_MEMORY", -5: "DTB_ERR_HIP", -6: "DTB_ERR_TIMEOUT", -7: "DTB_ERR_NOT_PLANNED",
@@ -44,6 +44,11 @@ class Grid(ctypes.Structure):
                 ("pitch", ctypes.c_int64)]
 
 
+class Grid3(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("depth", ctypes.c_int64), ("rows", ctypes.c_int64),
+                ("cols", ctypes.c_int64), ("pitch", ctypes.c_int64), ("plane_pitch", ctypes.c_int64)]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("ghost_k", ctypes.c_int32), ("depth_D", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("max_wg", ctypes.c_int32), ("exact", ctypes.c_int32),
@@ -59,7 +64,8 @@ class Problem(ctypes.Structure):
 # Every symbol include/dtb.h and include/dtb_testing.h declare.
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
            "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep",
-           "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing", "dtb_probe", "dtb_run_noalloc")
+           "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing", "dtb_probe", "dtb_run_noalloc", "dtb_plan3d",
+           "dtb_run3d_plan")
 TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
@@ -79,6 +85,11 @@ def load():
                              ctypes.c_int64, ctypes.POINTER(PlanOpts)]
     lib.dtb_run_plan.restype = ctypes.c_int
     lib.dtb_run_plan.argtypes = [P, ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, P]
+    lib.dtb_plan3d.restype = ctypes.c_int
+    lib.dtb_plan3d.argtypes = [ctypes.POINTER(P), ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                               ctypes.c_int64, ctypes.c_int, ctypes.POINTER(PlanOpts)]
+    lib.dtb_run3d_plan.restype = ctypes.c_int
+    lib.dtb_run3d_plan.argtypes = [P, ctypes.POINTER(Grid3), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, P]
     lib.dtb_run.restype = ctypes.c_int
     lib.dtb_run.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int, P]
     lib.dtb_run_batched.restype = ctypes.c_int
@@ -224,6 +235,44 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+def _grid3(t, cols=None) -> Grid3:
+    if t.dim() != 3 or not t.is_cuda:
+        raise ValueError("grid must be a 3-D device tensor of shape (depth + 2, rows + 2, pitch)")
+    if t.stride(2) != 1 or t.stride(1) < t.shape[2] or t.stride(0) < t.shape[1] * t.stride(1):
+        raise ValueError("grid rows must be contiguous and planes must not overlap")
+    cols = t.shape[2] - 2 if cols is None else int(cols)
+    return Grid3(t.data_ptr(), t.shape[0] - 2, t.shape[1] - 2, cols, t.stride(1), t.stride(0))
+
+
+class Plan3D(Plan):
+    """An explicit j3d7pt plan (dtb_plan3d / dtb_run3d_plan / dtb_plan_destroy)."""
+
+    def __init__(self, depth: int, rows: int, cols: int, pitch: int, plane_pitch: int, dtype: int,
+                 path: int = PATH_AUTO, ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0,
+                 exact: bool = False):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, 0, 0, 0, 0, 7)
+        _check(lib.dtb_plan3d(ctypes.byref(self._h), depth, rows, cols, pitch, plane_pitch, dtype, ctypes.byref(opts)),
+               "dtb_plan3d")
+        self.rows, self.cols, self.pitch, self.dtype = rows, cols, pitch, dtype
+        self.depth, self.plane_pitch, self.stencil = depth, plane_pitch, 7
+
+    def run(self, grid, coeffs, T: int, stream=None, cols=None):
+        """Advance the 3-D `grid` T steps in place: seven coefficients (c, n, s, e, w, t, b)."""
+        g = _grid3(grid, cols)
+        c = [float(x) for x in coeffs]
+        if len(c) != 7:
+            raise ValueError("seven coefficients (c, n, s, e, w, t, b) are required")
+        _check(load().dtb_run3d_plan(self._h, ctypes.byref(g), (ctypes.c_double * 7)(*c), int(T), _stream(stream)),
+               "dtb_run3d_plan")
+
+
+def plan3d_for(grid, cols=None, **opts) -> Plan3D:
+    g = _grid3(grid, cols)
+    return Plan3D(g.depth, g.rows, g.cols, g.pitch, g.plane_pitch, _dtype_of(grid), **opts)
 
 
 def plan_for(grid, T_hint: int = 0, cols=None, **opts) -> Plan:

@@ -200,7 +200,51 @@ WORKLOADS = {
 }
 
 
-def workload(name: str) -> Workload:
+@dataclass
+class Workload3:
+    """A named j3d7pt configuration (3-D grid, seven coefficients, step count)."""
+    name: str
+    depth: int
+    rows: int
+    cols: int
+    T: int
+    dtype: str
+    coeffs: tuple
+    halo: float
+    seed: int
+    note: str = ""
+    pts: int = 7
+
+    @property
+    def cell_updates(self) -> int:
+        return self.depth * self.rows * self.cols * self.T
+
+    def grid(self, pitch: int | None = None, dtype=np.float64) -> np.ndarray:
+        """The FP64 initial grid (the weights are drawn first from the same generator)."""
+        rng = np.random.default_rng(self.seed)
+        rng.dirichlet(np.ones(7))
+        return uniform_grid3(self.depth, self.rows, self.cols, rng, self.halo, pitch, dtype)
+
+
+def _mk3(name, depth, rows, cols, T, dtype, halo, seed, note=""):
+    return Workload3(name, depth, rows, cols, T, dtype, weights7(seed), halo, seed, note)
+
+
+WORKLOADS3 = {
+    w.name: w for w in [
+        _mk3("j3d7pt_256x256x256_f64_T30", 256, 256, 256, 30, "f64", 0.5, 9,
+             "3-D seven-point, 128 MiB: several z-blocks per column"),
+        _mk3("j3d7pt_512x512x512_f64_T60", 512, 512, 512, 60, "f64", 0.0, 10,
+             "3-D seven-point, 1 GiB FP64: far larger than the chip"),
+        _mk3("j3d7pt_512x512x512_f32_T60", 512, 512, 512, 60, "f32", 0.0, 10,
+             "3-D seven-point, FP32 (same input as the FP64 run)"),
+    ]
+}
+
+
+def workload(name: str):
+    if name in WORKLOADS3:
+        return WORKLOADS3[name]
     return WORKLOADS[name]
 
 

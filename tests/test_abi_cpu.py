@@ -17,7 +17,7 @@ def _declared():
     for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
         text = open(h).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names.update(re.findall(r"\b(dtb_[a-z_]+)\s*\(", text))
+        names.update(re.findall(r"\b(dtb_[a-z0-9_]+)\s*\(", text))
     return names
 
 
@@ -128,9 +128,9 @@ def test_plan_rejects_bad_sync_and_overlapped_options():
 
 
 def test_plan_box_stencil_options_checked_on_the_host():
-    """stencil must be 0, 5 or 9; the box has no overlapped path, no half-height or grid-barrier variant, and
+    """stencil must be 0, 5, 7 or 9; the box has no overlapped path, no half-height or grid-barrier variant, and
     only its own register tiles (FP64 8 rows per lane, FP32 16)."""
-    for bad in (1, 7, 25, -5):
+    for bad in (1, 8, 25, -5):  # 7 (j3d7pt) is a 3-D plan: refused as unsupported below
         o = dtb.PlanOpts()
         o.stencil = bad
         assert _plan_rc(64, 64, 66, 0, o) == -1, bad
@@ -155,3 +155,41 @@ def test_box_plan_takes_nine_coefficients():
     with pytest.raises(ValueError):
         dtb._coeffs([0.1] * 9, 5)
     assert len(dtb._coeffs([0.1] * 9, 9)) == 9
+
+
+def test_plan3d_rejects_bad_shapes_and_options_before_any_hip_call():
+    lib = dtb.load()
+    h = ctypes.c_void_p()
+
+    def rc(depth, rows, cols, pitch, pp, dtype=0, **fields):
+        o = dtb.PlanOpts()
+        for k, v in fields.items():
+            setattr(o, k, v)
+        return lib.dtb_plan3d(ctypes.byref(h), depth, rows, cols, pitch, pp, dtype, ctypes.byref(o))
+
+    assert lib.dtb_plan3d(None, 4, 4, 4, 6, 36, 0, None) == -1
+    for bad in [(0, 4, 4, 6, 36), (4, 0, 4, 6, 36), (4, 4, 0, 6, 36), (4, 4, 4, 5, 36), (4, 4, 4, 6, 35)]:
+        assert rc(*bad) == -1, bad
+    assert rc(4, 4, 4, 6, 36, dtype=3) == -1
+    assert rc(4, 4, 4, 6, 36, stencil=9) == -1            # a 3-D plan is j3d7pt
+    for fields in (dict(path=dtb.PATH_RESIDENT), dict(path=dtb.PATH_SWEEP), dict(ghost_k=4), dict(sync=1),
+                   dict(tune=1), dict(waves=4), dict(debug_flags=dtb.DEBUG_POISON)):
+        assert rc(4, 4, 4, 6, 36, **fields) == -2, fields
+    # and a 2-D plan refuses the 3-D stencil and path
+    assert _plan_rc(64, 64, 66, 0, _opts(stencil=7)) == -2
+    assert _plan_rc(64, 64, 66, 0, _opts(path=dtb.PATH_STREAM3D)) == -2
+
+
+def _opts(**fields):
+    o = dtb.PlanOpts()
+    for k, v in fields.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_run3d_rejects_bad_arguments():
+    lib = dtb.load()
+    c = (ctypes.c_double * 7)(*([1.0 / 7] * 7))
+    g = dtb.Grid3(0x1000, 4, 4, 4, 6, 36)
+    assert lib.dtb_run3d_plan(None, ctypes.byref(g), c, 1, None) == -1
+    assert lib.dtb_run3d_plan(None, None, c, 1, None) == -1
