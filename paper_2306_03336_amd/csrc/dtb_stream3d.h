@@ -16,8 +16,8 @@
 // 0 .. K-1, the three most recent planes of that level in registers (the
 // "2.5D" window: rows across waves, columns across lanes, planes across
 // registers), so that level l+1 of plane q is computed as soon as level l of
-// plane q+1 exists.  Level 0 is loaded from HBM (one plane ahead, so that the
-// load overlaps the compute), level K is stored.  Neighbouring workgroups do
+// plane q+1 exists.  Level 0 is loaded from HBM (two planes ahead, so that
+// the loads overlap the compute), level K is stored.  Neighbouring workgroups do
 // not synchronise: each tile carries a K-deep ring of redundant cells in x and
 // y, and each z-block K planes below and above (overlapped, or trapezoidal,
 // blocking in all three axes; stale values from a tile's open edges move one
@@ -90,7 +90,7 @@ template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE>
 struct Stream3 {
     using G = Stream3Geo<T, C, R, K, WAVES>;
     T win[K][3][R][C];   // level l's three most recent planes (slot: the plane's offset from the first, mod 3)
-    T next[R][C];        // the level-0 plane being loaded one iteration ahead
+    T next[2][R][C];     // the level-0 planes being loaded one and two iterations ahead
     Coef7<T> k;
     T* lds;
     int wave, lane;
@@ -98,6 +98,8 @@ struct Stream3 {
     int col0;            // storage column of this lane's slot 0
     bool rowact[R];      // EDGE: row inside the interior
     bool colact[C];      // EDGE: column inside the interior
+    bool rowown[R];      // row owned by this tile (stored)
+    bool colown[C];      // column owned by this tile
 
     __device__ __forceinline__ T* edge_row(int parity, int level, int w, int bottom)
     {
@@ -139,6 +141,13 @@ struct Stream3 {
                                             const T (&above)[C], const T (&below)[C], bool plane_interior,
                                             T (&out)[R][C])
     {
+        if (!plane_interior) {  // a halo plane (uniform): it keeps its values at every level
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < C; ++c) out[r][c] = cw[r][c];
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const T wl = wave_shr1_3(cw[r][C - 1]);
@@ -151,13 +160,13 @@ struct Stream3 {
                 const T N = r == R - 1 ? below[c] : cw[r + 1][c];
                 T v = j3d7pt<FMA>(W, E, S, cw[r][c], N, bw[r][c], aw[r][c], k);
                 if constexpr (EDGE) v = (rowact[r] && colact[c]) ? v : cw[r][c];
-                out[r][c] = plane_interior ? v : cw[r][c];
+                out[r][c] = v;
             }
         }
     }
 };
 
-// Slot of plane p0 + 3m + u - l in a level's three-slot window (u, l known at compile time after unrolling).
+// Slot of plane p0 + 6m + u - l in a level's three-slot window (u, l known at compile time after unrolling).
 __host__ __device__ constexpr int stream_slot(int u, int l) { return ((u - l) % 3 + 3) % 3; }
 
 // One K-step launch of one workgroup: tile `d`, owned planes [zo0, zo1).
@@ -176,19 +185,25 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
     for (int r = 0; r < R; ++r) s.rowact[r] = s.g0 + r >= 1 && s.g0 + r <= A.rows;
 #pragma unroll
     for (int c = 0; c < C; ++c) s.colact[c] = s.col0 + c >= 1 && s.col0 + c <= A.cols;
+#pragma unroll
+    for (int r = 0; r < R; ++r) s.rowown[r] = s.g0 + r >= d.own_r0 && s.g0 + r < d.own_r1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) s.colown[c] = s.col0 + c >= d.own_c0 && s.col0 + c < d.own_c1;
     const T* src = (const T*)A.src;
     T* dst = (T*)A.dst;
     // Level 0 (loaded) covers planes [p0, p_end); level l covers [lo(l), hi(l)), one plane less on each
     // side per level, clipped to the stored planes 0 .. depth + 1; level K is [zo0, zo1).
     const int p0 = zo0 - K > 0 ? zo0 - K : 0;
     const int p_end = zo1 + K < A.depth + 2 ? zo1 + K : A.depth + 2;
-    s.load_plane(src, A, p0, s.next);
+    s.load_plane(src, A, p0, s.next[0]);
+    if (p0 + 1 < p_end) s.load_plane(src, A, p0 + 1, s.next[1]);
     // Iteration p: level 0 takes plane p, level l = 1 .. K produces plane p - l (when it has one); the
     // last owned plane, zo1 - 1, leaves level K at iteration zo1 - 1 + K.
+    // Unrolled by six: window slots repeat every three planes, prefetch buffers every two.
     const int p_stop = zo1 + K;
-    for (int pb = p0; pb < p_stop; pb += 3) {
+    for (int pb = p0; pb < p_stop; pb += 6) {
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
+        for (int u = 0; u < 6; ++u) {
             const int p = pb + u;
             if (p >= p_stop) break;
             const int par = p & 1;
@@ -196,8 +211,8 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
 #pragma unroll
                 for (int r = 0; r < R; ++r)
 #pragma unroll
-                    for (int c = 0; c < C; ++c) s.win[0][stream_slot(u, 0)][r][c] = s.next[r][c];
-                if (p + 1 < p_end) s.load_plane(src, A, p + 1, s.next);
+                    for (int c = 0; c < C; ++c) s.win[0][stream_slot(u, 0)][r][c] = s.next[u % 2][r][c];
+                if (p + 2 < p_end) s.load_plane(src, A, p + 2, s.next[u % 2]);
             }
             // The centre planes' edge rows were published last iteration (the other LDS buffer).
             __syncthreads();
@@ -227,13 +242,11 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
                     T* plane = dst + (int64_t)q * A.plane_pitch;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const int g = s.g0 + r;
-                        if (g < d.own_r0 || g >= d.own_r1) continue;
+                        if (!s.rowown[r]) continue;  // uniform over the wave
+                        T* row = plane + (int64_t)(s.g0 + r) * A.pitch + s.col0;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            const int col = s.col0 + c;
-                            if (col >= d.own_c0 && col < d.own_c1) plane[(int64_t)g * A.pitch + col] = out[r][c];
-                        }
+                        for (int c = 0; c < C; ++c)
+                            if (s.colown[c]) row[c] = out[r][c];
                     }
                 }
             }

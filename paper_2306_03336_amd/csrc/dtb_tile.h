@@ -792,7 +792,7 @@ __device__ __forceinline__ bool spin_until(uint32_t* p, uint32_t target, int* er
 }
 
 __device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err, uint32_t spin_limit,
-                                             bool release = false, bool wait_stores = true)
+                                             bool release = false, bool wait_stores = true, bool acquire = false)
 {
     // wait_stores == false: the workgroup's outstanding stores need not be
     // complete at the barrier (the caller's memory accesses that the barrier
@@ -832,6 +832,9 @@ __device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
     }
+    // acquire: what other workgroups released before the barrier is visible to
+    // this workgroup's plain loads after it (no stale line of this XCD's caches).
+    if (acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // The synchronisation at an exchange point: by default each workgroup waits
@@ -1245,8 +1248,10 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepAr
     // next tile's exchanges from overwriting strips of this one that a slower
     // workgroup may still read: it does not wait for this tile's stores to B,
     // which drain while the next tile loads.  B is read in the next round only:
-    // the round's last barrier waits for the stores and makes them visible to
-    // every XCD (agent-scope release).
+    // the round's last barrier waits for the stores, makes them visible to
+    // every XCD (agent-scope release) and, past the barrier, drops whatever
+    // this XCD's caches hold of them (agent-scope acquire), so that the next
+    // round loads A with plain (wide) loads.
     for (int round = 0; round < S.nrounds; ++round) {
         const T* A = (const T*)S.bufs[round & 1];
         T* B = (T*)S.bufs[(round + 1) & 1];
@@ -1259,16 +1264,17 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepAr
                 const int64_t per = (steps + P.k - 1) / P.k - 1;
                 epoch += per > 0 ? (uint32_t)per : 1u;
             } else if (halo_varies<T, C, R, WAVES, COLMASK, PTS>(P, d)) {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, true, true, PTS>(P, d, A, B, steps, me, flags,
-                                                                                           base, epoch, err, spin_limit, lds);
-            } else {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, true, true, PTS>(P, d, A, B, steps, me, flags,
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false, true, PTS>(P, d, A, B, steps, me, flags,
                                                                                             base, epoch, err, spin_limit, lds);
+            } else {
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false, true, PTS>(P, d, A, B, steps, me,
+                                                                                             flags, base, epoch, err,
+                                                                                             spin_limit, lds);
             }
             ++nbar;
             const bool end_of_round = tile + 1 == S.ntiles;
             const uint64_t tb = P.timing ? __builtin_amdgcn_s_memrealtime() : 0;
-            grid_barrier(S.bar, nbar, err, spin_limit, end_of_round, end_of_round);
+            grid_barrier(S.bar, nbar, err, spin_limit, end_of_round, end_of_round, end_of_round);
             if (P.timing) add_clock(P, me, kTimeBarrier, tb);
         }
         done += steps;
