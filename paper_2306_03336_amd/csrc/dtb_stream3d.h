@@ -16,8 +16,8 @@
 // 0 .. K-1, the three most recent planes of that level in registers (the
 // "2.5D" window: rows across waves, columns across lanes, planes across
 // registers), so that level l+1 of plane q is computed as soon as level l of
-// plane q+1 exists.  Level 0 is loaded from HBM (two planes ahead, so that
-// the loads overlap the compute), level K is stored.  Neighbouring workgroups do
+// plane q+1 exists.  Level 0 is loaded from HBM (one or two planes ahead, so
+// that the loads overlap the compute), level K is stored.  Neighbouring workgroups do
 // not synchronise: each tile carries a K-deep ring of redundant cells in x and
 // y, and each z-block K planes below and above (overlapped, or trapezoidal,
 // blocking in all three axes; stale values from a tile's open edges move one
@@ -86,11 +86,11 @@ struct Stream3Geo {
 };
 
 // The register pipeline of one workgroup.
-template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE>
+template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE, int PF>
 struct Stream3 {
     using G = Stream3Geo<T, C, R, K, WAVES>;
     T win[K][3][R][C];   // level l's three most recent planes (slot: the plane's offset from the first, mod 3)
-    T next[2][R][C];     // the level-0 planes being loaded one and two iterations ahead
+    T next[PF][R][C];    // the level-0 planes being loaded 1 .. PF iterations ahead
     Coef7<T> k;
     T* lds;
     int wave, lane;
@@ -166,14 +166,18 @@ struct Stream3 {
     }
 };
 
-// Slot of plane p0 + 6m + u - l in a level's three-slot window (u, l known at compile time after unrolling).
+// Slot of plane p0 + Um + u - l in a level's three-slot window (U a multiple of 3; u, l known at compile time
+// after unrolling).
 __host__ __device__ constexpr int stream_slot(int u, int l) { return ((u - l) % 3 + 3) % 3; }
 
 // One K-step launch of one workgroup: tile `d`, owned planes [zo0, zo1).
-template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE>
+// PF: planes loaded ahead (1 or 2).  Measured at 512^3: FP32 gains from two (519 -> 537 GCells/s), FP64,
+// whose launch is bound by HBM traffic, loses (518 -> 485) to the extra registers.
+template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE, int PF = (sizeof(T) == 4 ? 2 : 1)>
 __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Desc& d, int zo0, int zo1, T* lds)
 {
-    Stream3<T, C, R, K, WAVES, FMA, EDGE> s;
+    static_assert(PF == 1 || PF == 2, "one or two planes ahead");
+    Stream3<T, C, R, K, WAVES, FMA, EDGE, PF> s;
     s.lds = lds;
     s.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     s.lane = threadIdx.x & 63;
@@ -196,14 +200,17 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
     const int p0 = zo0 - K > 0 ? zo0 - K : 0;
     const int p_end = zo1 + K < A.depth + 2 ? zo1 + K : A.depth + 2;
     s.load_plane(src, A, p0, s.next[0]);
-    if (p0 + 1 < p_end) s.load_plane(src, A, p0 + 1, s.next[1]);
+    if constexpr (PF == 2) {
+        if (p0 + 1 < p_end) s.load_plane(src, A, p0 + 1, s.next[1]);
+    }
     // Iteration p: level 0 takes plane p, level l = 1 .. K produces plane p - l (when it has one); the
     // last owned plane, zo1 - 1, leaves level K at iteration zo1 - 1 + K.
-    // Unrolled by six: window slots repeat every three planes, prefetch buffers every two.
+    // Unrolled by three (six with two prefetch buffers): window slots repeat every three planes.
+    constexpr int U = PF == 2 ? 6 : 3;
     const int p_stop = zo1 + K;
-    for (int pb = p0; pb < p_stop; pb += 6) {
+    for (int pb = p0; pb < p_stop; pb += U) {
 #pragma unroll
-        for (int u = 0; u < 6; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int p = pb + u;
             if (p >= p_stop) break;
             const int par = p & 1;
@@ -211,8 +218,8 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
 #pragma unroll
                 for (int r = 0; r < R; ++r)
 #pragma unroll
-                    for (int c = 0; c < C; ++c) s.win[0][stream_slot(u, 0)][r][c] = s.next[u % 2][r][c];
-                if (p + 2 < p_end) s.load_plane(src, A, p + 2, s.next[u % 2]);
+                    for (int c = 0; c < C; ++c) s.win[0][stream_slot(u, 0)][r][c] = s.next[u % PF][r][c];
+                if (p + PF < p_end) s.load_plane(src, A, p + PF, s.next[u % PF]);
             }
             // The centre planes' edge rows were published last iteration (the other LDS buffer).
             __syncthreads();
