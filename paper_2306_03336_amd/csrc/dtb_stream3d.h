@@ -100,6 +100,7 @@ struct Stream3 {
     bool colact[C];      // EDGE: column inside the interior
     bool rowown[R];      // row owned by this tile (stored)
     bool colown[C];      // column owned by this tile
+    bool allown;         // all C columns owned
 
     __device__ __forceinline__ T* edge_row(int parity, int level, int w, int bottom)
     {
@@ -193,6 +194,7 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
     for (int r = 0; r < R; ++r) s.rowown[r] = s.g0 + r >= d.own_r0 && s.g0 + r < d.own_r1;
 #pragma unroll
     for (int c = 0; c < C; ++c) s.colown[c] = s.col0 + c >= d.own_c0 && s.col0 + c < d.own_c1;
+    s.allown = s.col0 >= d.own_c0 && s.col0 + C <= d.own_c1;
     const T* src = (const T*)A.src;
     T* dst = (T*)A.dst;
     // Level 0 (loaded) covers planes [p0, p_end); level l covers [lo(l), hi(l)), one plane less on each
@@ -251,9 +253,19 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
                     for (int r = 0; r < R; ++r) {
                         if (!s.rowown[r]) continue;  // uniform over the wave
                         T* row = plane + (int64_t)(s.g0 + r) * A.pitch + s.col0;
+                        if (s.allown) {
+                            // every cell of the lane owned: one wide store of its C cells (aligned to the
+                            // element only: the hardware takes unaligned wide accesses to global memory)
+                            typedef T Vec __attribute__((ext_vector_type(C), aligned(sizeof(T))));
+                            Vec v;
 #pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            if (s.colown[c]) row[c] = out[r][c];
+                            for (int c = 0; c < C; ++c) v[c] = out[r][c];
+                            *(Vec*)row = v;
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < C; ++c)
+                                if (s.colown[c]) row[c] = out[r][c];
+                        }
                     }
                 }
             }
