@@ -51,6 +51,16 @@ int32_t dtb_test_layout(int64_t rows, int64_t cols, int32_t rows_per_lane, int32
 int32_t dtb_test_sweep(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_t cols_per_lane, int32_t waves,
                        int32_t k, int32_t D, int32_t max_wg, int32_t n_xcd, int32_t* out, int32_t max_records);
 
+/*
+ * The 3-D streaming planner's split of one axis of n interior cells (storage
+ * 0 .. n+1) into overlapping ranges of E cells with K-deep rings at open
+ * edges (dtb_plan3d): writes up to max_spans triples (e0, own0, own1) -- the
+ * range [e0, e0 + E) and its owned part [own0, own1) -- and returns the number
+ * of ranges (more than max_spans: nothing written), or -1 if E < 2K + 1 or an
+ * argument is invalid.  Host only.
+ */
+int32_t dtb_test_split3(int64_t n, int32_t E, int32_t K, int32_t* out, int32_t max_spans);
+
 #define DTB_TEST_BATCH_STRIDE 13
 
 /*

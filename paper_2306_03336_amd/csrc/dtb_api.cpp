@@ -1541,4 +1541,19 @@ int32_t dtb_test_sweep(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_
     return (int32_t)nrec;
 }
 
+int32_t dtb_test_split3(int64_t n, int32_t E, int32_t K, int32_t* out, int32_t max_spans)
+{
+    if (max_spans < 0 || (max_spans > 0 && !out)) return -1;
+    std::vector<Span3> spans;
+    if (!split_axis3(n, E, K, &spans)) return -1;
+    const int32_t ns = (int32_t)spans.size();
+    if (ns > max_spans) return ns;
+    for (int32_t i = 0; i < ns; ++i) {
+        out[3 * i] = spans[i].e0;
+        out[3 * i + 1] = spans[i].own0;
+        out[3 * i + 2] = spans[i].own1;
+    }
+    return ns;
+}
+
 }  // extern "C"

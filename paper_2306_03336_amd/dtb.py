@@ -65,7 +65,7 @@ class Problem(ctypes.Structure):
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
            "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep",
            "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing", "dtb_probe", "dtb_run_noalloc", "dtb_plan3d",
-           "dtb_run3d_plan")
+           "dtb_run3d_plan", "dtb_test_split3")
 TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
@@ -90,6 +90,9 @@ def load():
                                ctypes.c_int64, ctypes.c_int, ctypes.POINTER(PlanOpts)]
     lib.dtb_run3d_plan.restype = ctypes.c_int
     lib.dtb_run3d_plan.argtypes = [P, ctypes.POINTER(Grid3), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, P]
+    lib.dtb_test_split3.restype = ctypes.c_int32
+    lib.dtb_test_split3.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.c_int32]
     lib.dtb_run.restype = ctypes.c_int
     lib.dtb_run.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int, P]
     lib.dtb_run_batched.restype = ctypes.c_int
@@ -340,6 +343,17 @@ def test_layout(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, wa
                         nb=[x for x in o[7:7 + o[6]]], narrow_rows=bool(o[7 + TEST_MAX_NEIGHBOURS] & 1),
                         narrow_cols=bool(o[7 + TEST_MAX_NEIGHBOURS] & 2)))
     return out
+
+
+def test_split3(n: int, E: int, K: int):
+    """3-D streaming planner's split of one axis, without a GPU: list of (e0, own0, own1), or None."""
+    lib = load()
+    m = lib.dtb_test_split3(n, E, K, None, 0)
+    if m < 0:
+        return None
+    buf = (ctypes.c_int32 * (3 * m))()
+    assert lib.dtb_test_split3(n, E, K, buf, m) == m
+    return [tuple(buf[3 * i:3 * i + 3]) for i in range(m)]
 
 
 def test_sweep(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, waves: int, k: int, D: int,

@@ -227,3 +227,27 @@ def test_batch_autotuner_picks_per_grid():
     assert (jobs[0]["R"], jobs[0]["C"], jobs[0]["g"], jobs[0]["k"]) == (16, 2, 31, 16)
     jobs = _check_batch([(60, 3000, 0, 500)], n_slots=24, r64=0, r32=0)
     assert (jobs[0]["R"], jobs[0]["C"]) == (8, 4) and jobs[0]["g"] <= 24
+
+
+@pytest.mark.parametrize("n,E,K", [(1, 32, 3), (5, 32, 3), (31, 32, 3), (32, 32, 3), (33, 32, 3), (100, 32, 3),
+                                   (512, 32, 3), (512, 128, 3), (513, 128, 2), (1000, 256, 1), (7, 7, 3), (64, 7, 3)])
+def test_split3_covers_axis_with_deep_enough_rings(n, E, K):
+    """The 3-D streaming split: owned parts tile 1 .. n exactly, in order; each range holds its owned part; an
+    owned part keeps K cells from every open edge of its range (an edge at the storage ends 0 / n+1 is closed:
+    the range holds the halo there)."""
+    spans = dtb.test_split3(n, E, K)
+    assert spans, (n, E, K)
+    assert spans[0][1] == 1 and spans[-1][2] == n + 1
+    for (e0, o0, o1), nxt in zip(spans, spans[1:] + [None]):
+        assert o0 < o1 and e0 >= 0
+        if nxt is not None:
+            assert nxt[1] == o1
+        lo_open = e0 > 0              # cells below the range exist (not the halo row 0 inside it)
+        hi_open = e0 + E < n + 2      # the range ends before the far halo row n + 1
+        assert o0 - e0 >= (K if lo_open else 1)
+        assert e0 + E - o1 >= (K if hi_open else 0)
+
+
+def test_split3_refuses_short_ranges():
+    assert dtb.test_split3(100, 6, 3) is None     # E < 2K + 1
+    assert dtb.test_split3(0, 32, 3) is None
