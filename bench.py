@@ -213,6 +213,22 @@ def _rooflines(gc, dtype, desc, T, updates, dtb_ms, den, flops=FLOPS_PER_UPDATE)
     return r
 
 
+def _same_size_copy_GBs(torch, stream, like, launches=20):
+    """Copy rate of a plain elementwise copy of a buffer the size of `like`, one launch per copy, launches
+    back to back (what a one-step kernel does each step: read the grid once, write it once): bytes read and
+    written per launch over the median launch time."""
+    src = torch.ones_like(like)
+    dst = torch.empty_like(like)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    ms = _time_runs(lambda: torch.mul(src, 1.0, out=dst), torch, stream, launches)
+    ms.sort()
+    med = ms[len(ms) // 2]
+    nbytes = 2 * like.numel() * like.element_size()
+    del src, dst
+    return round(nbytes / (med / 1e3) / 1e9, 1)
+
+
 def _one_config(dtb, inputs, torch, np, stream, name, records, den, reps=5):
     w = inputs.workload(name)
     dt = torch.float64 if w.dtype == "f64" else torch.float32
@@ -227,6 +243,7 @@ def _one_config(dtb, inputs, torch, np, stream, name, records, den, reps=5):
     d = plan.describe()
     plan.destroy()
     launches, graph_ms = _step_baseline(dtb, torch, stream, g, u0, w.coeffs, w.T, reps, w.pts)
+    same_copy = _same_size_copy_GBs(torch, stream, u0)
     del g, u0
     torch.cuda.empty_cache()
     updates = w.cell_updates
@@ -247,6 +264,8 @@ def _one_config(dtb, inputs, torch, np, stream, name, records, den, reps=5):
     if den.get(copy_key):
         base["frac_of_measured_copy_bandwidth"] = round(base["achieved_GBs_algorithmic"] / den[copy_key], 3)
         base["copy_reference"] = copy_key
+    base["same_size_copy_per_launch_GBs"] = same_copy
+    base["frac_of_same_size_copy"] = round(base["achieved_GBs_algorithmic"] / same_copy, 3)
     return {"workload": name, "dtype": w.dtype, "T": w.T, "cell_updates": updates, "plan": d, "dtb": st,
             "step_kernel": base, "dtb_speedup": round(base["median_ms"] / st["median_ms"], 3),
             "roofline": _rooflines(st["GCells_per_s"], w.dtype, d, w.T, updates, st["median_ms"], den,
@@ -533,6 +552,9 @@ def main() -> int:
                 "launches": w.T, "dtb_speedup": round(value / bval, 3),
                 "hbm_roofline_GCells": PEAK_HBM_GBS / (2 * b),
                 "achieved_GBs_algorithmic": round(bval * 2 * b, 1)}
+        same = _same_size_copy_GBs(torch, stream, u0)
+        base["same_size_copy_per_launch_GBs"] = same
+        base["frac_of_same_size_copy"] = round(base["achieved_GBs_algorithmic"] / same, 3)
         print(f"[bench] one-step kernel: {bval:.1f} GCells/s", file=sys.stderr, flush=True)
 
     if args.copy_probe_mb > 0:
