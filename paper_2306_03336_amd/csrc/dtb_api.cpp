@@ -24,7 +24,7 @@ using namespace dtb;
 namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // bounded wait: a few seconds of polling
-constexpr size_t kBarrierWords = 17 * (size_t)kFlagStride;  // device-wide barrier counters, one slot each
+constexpr size_t kBarrierWords = kBarrierSlots * (size_t)kFlagStride;  // device-wide barrier counters, one slot each
 constexpr int kNumXcd = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
 // Instantiated rows per lane: FP64 8, 16, 24 (2 columns per lane) and 12 (4 columns); FP32 8, 16, 24, 28.
 constexpr int kDtbRowsPerLane[] = {8, 12, 16, 24, 28};
@@ -227,14 +227,15 @@ bool choose_resident(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts&
 
 // Model of one time step of the sweep, in microseconds: every big tile runs
 // D steps on the whole chip (VALU time of one register tile per step), one
-// exchange every k steps, one device-wide barrier, and its HBM traffic (load
-// of the computed region, store of the valid part) once per D steps.
+// exchange every k steps, a fixed cost per big tile (the tile load's latency
+// and the synchronisation between big tiles), and its HBM traffic (load of
+// the computed region, store of the valid part) once per D steps.
 double sweep_step_us(const SweepPlan& sp, int dtype, int pts)
 {
     const int eb = dtype == DTB_F64 ? 8 : 4;
     const double t_step = tile_step_time_us(sp.ER, sp.EC, eb, pts);
     const double t_exch = exchange_time_us(sp.ER, sp.EC, sp.R, sp.C, eb, exchange_staged(sp.R, sp.C, eb, sp.k));
-    const double t_bar = 10.0;  // device-wide barrier plus the tile load's latency, per big tile
+    const double t_bar = 10.0;  // per big tile: the tile load's latency and the barrier between big tiles
     const double hbm_bytes_per_us = 4.0e6;
     const double b = dtype == DTB_F64 ? 8.0 : 4.0;
     double total = 0;

@@ -27,6 +27,10 @@ constexpr bool exchange_staged(int R, int C, int elem_bytes, int k)
 // channels, so polling workgroups do not queue on one channel.
 constexpr int kFlagStride = 1024;
 
+// Device-wide barrier counters of the tile-serial sweep (and of the
+// grid-barrier design): slots kFlagStride apart, reset before every launch.
+constexpr int kBarrierSlots = 18;
+
 // One problem of a launch: a grid advanced T steps in place.
 //
 // Storage (same for grid and the two exchange buffers): (rows + 2) lines of

@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_copy_halo(const T* __restrict__ src, T*
 // Zeroes the sweep's barrier counters (kBarrierSlots slots, kFlagStride apart).
 __global__ void k_reset_counter(uint32_t* bar)
 {
-    if (threadIdx.x < 17) __hip_atomic_store(bar + (size_t)threadIdx.x * kFlagStride, 0u, __ATOMIC_RELAXED,
+    if (threadIdx.x < kBarrierSlots) __hip_atomic_store(bar + (size_t)threadIdx.x * kFlagStride, 0u, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -775,7 +775,10 @@ __device__ __forceinline__ void exchange_point(uint32_t* flags, int me, const Wg
 // arrival of an XCD bumps the XCD counter, waits for every XCD, then releases
 // its own XCD by writing n.  Prior device-scope stores are complete (vmcnt 0)
 // before arriving.  Bounded waits as in exchange_point.
-constexpr int kBarrierSlots = 17;
+// Slot 17 (of kBarrierSlots): the tile-serial sweep's count of tile-boundary
+// arrivals (the split-phase barrier between the big tiles of a round, below).
+constexpr int kTileCountSlot = 17;
+static_assert(kTileCountSlot < kBarrierSlots, "barrier slots");
 
 __device__ __forceinline__ bool spin_until(uint32_t* p, uint32_t target, int* err, int code, uint32_t spin_limit)
 {
@@ -835,6 +838,42 @@ __device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err
     // acquire: what other workgroups released before the barrier is visible to
     // this workgroup's plain loads after it (no stale line of this XCD's caches).
     if (acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Split-phase barrier between two big tiles of one round of the sweep.  The
+// only thing it orders is the reuse of the exchange buffers: no workgroup may
+// store the strips of big tile m while another one may still read strips of
+// big tile m - 1 (tile m reads buffer A, which no one writes in this round,
+// and stores its own cells of buffer B, so nothing else needs it).  Every
+// workgroup adds one to a single counter when it is done with a big tile
+// (its ring loads have all returned by then), and before it works on the next
+// big tile of the round it waits until the counter has reached
+// nwg * (boundaries so far, counted over the whole launch).  The first time
+// the counter reaches nwg * m every workgroup has arrived exactly m times,
+// since none arrives an (m + 1)-th time before it has waited for nwg * m.
+// The wait is read once before the tile load is issued and checked after it
+// (the loads hide the round trip); only if the count is short does thread 0
+// keep polling (bounded, as in grid_barrier).
+__device__ __forceinline__ void tile_arrive(uint32_t* bar)
+{
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(bar + (size_t)kTileCountSlot * kFlagStride, 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t tile_count_peek(uint32_t* bar)
+{
+    return threadIdx.x == 0 ? __hip_atomic_load(bar + (size_t)kTileCountSlot * kFlagStride, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : 0u;
+}
+
+__device__ __forceinline__ void tile_wait(uint32_t* bar, uint32_t seen, uint32_t target, int* err,
+                                          uint32_t spin_limit)
+{
+    if (threadIdx.x == 0 && !reached(seen, target))
+        spin_until(bar + (size_t)kTileCountSlot * kFlagStride, target, err, 2, spin_limit);
+    __syncthreads();
 }
 
 // The synchronisation at an exchange point: by default each workgroup waits
@@ -1119,14 +1158,23 @@ template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWC
           bool STAGED = true, int PTS = 5>
 __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int64_t steps,
                                             int me, uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
-                                            uint32_t spin_limit, char* lds)
+                                            uint32_t spin_limit, char* lds, uint32_t* tile_bar = nullptr,
+                                            uint32_t tile_target = 0)
 {
     using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, PTS>;
     Tl t;
     const bool timing = P.timing != nullptr;  // DTB_DEBUG_TIMING (uniform branch)
     uint64_t t0 = timing ? __builtin_amdgcn_s_memrealtime() : 0;
+    // tile_target != 0: the split-phase barrier of the sweep (tile_wait) must
+    // have been passed before this segment's first strip store.
+    const uint32_t seen = tile_target != 0 ? tile_count_peek(tile_bar) : 0u;
     load_tile<SWEEP>(t, P, d, src, lds);
     if (timing) add_clock(P, me, kTimeLoad, t0);
+    if (tile_target != 0) {
+        if (timing) t0 = __builtin_amdgcn_s_memrealtime();
+        tile_wait(tile_bar, seen, tile_target, err, spin_limit);
+        if (timing) add_clock(P, me, kTimeBarrier, t0);
+    }
     run_epochs<HALO_ROWS, STAGED>(t, P, d, steps, me, flags, base, epoch, err, spin_limit);
     if (timing) t0 = __builtin_amdgcn_s_memrealtime();
     t.store_owned(t.a, dst, P.pitch, d);
@@ -1246,12 +1294,14 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepAr
     // Within a round the big tiles are independent (each reads A and writes its
     // own valid part of B), so the barrier between two of them only keeps the
     // next tile's exchanges from overwriting strips of this one that a slower
-    // workgroup may still read: it does not wait for this tile's stores to B,
-    // which drain while the next tile loads.  B is read in the next round only:
-    // the round's last barrier waits for the stores, makes them visible to
-    // every XCD (agent-scope release) and, past the barrier, drops whatever
-    // this XCD's caches hold of them (agent-scope acquire), so that the next
-    // round loads A with plain (wide) loads.
+    // workgroup may still read: a split-phase barrier (tile_arrive, then
+    // tile_wait after the next tile's load) that does not wait for this
+    // tile's stores to B, which drain while the next tile loads.  B is read in
+    // the next round only: the round's last barrier waits for the stores,
+    // makes them visible to every XCD (agent-scope release) and, past the
+    // barrier, drops whatever this XCD's caches hold of them (agent-scope
+    // acquire), so that the next round loads A with plain (wide) loads.
+    uint32_t nbound = 0;  // tile boundaries inside rounds so far (split-phase barrier)
     for (int round = 0; round < S.nrounds; ++round) {
         const T* A = (const T*)S.bufs[round & 1];
         T* B = (T*)S.bufs[(round + 1) & 1];
@@ -1259,23 +1309,32 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepAr
         const int64_t steps = left < S.D ? left : S.D;
         for (int tile = 0; tile < S.ntiles; ++tile) {
             const WgDesc& d = table[(size_t)tile * S.nwg + me];
+            // Past the first big tile of a round, wait for every workgroup to
+            // be done with the previous one (tile_wait) before storing strips.
+            const uint32_t target = tile > 0 ? nbound * gridDim.x : 0u;
             if (d.own_r0 == d.own_r1) {
                 // Idle for this tile: keep the epoch count in step with the others.
                 const int64_t per = (steps + P.k - 1) / P.k - 1;
                 epoch += per > 0 ? (uint32_t)per : 1u;
+                if (target != 0) tile_wait(S.bar, tile_count_peek(S.bar), target, err, spin_limit);
             } else if (halo_varies<T, C, R, WAVES, COLMASK, PTS>(P, d)) {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false, true, PTS>(P, d, A, B, steps, me, flags,
-                                                                                            base, epoch, err, spin_limit, lds);
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false, true, PTS>(
+                    P, d, A, B, steps, me, flags, base, epoch, err, spin_limit, lds, S.bar, target);
             } else {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false, true, PTS>(P, d, A, B, steps, me,
-                                                                                             flags, base, epoch, err,
-                                                                                             spin_limit, lds);
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false, true, PTS>(
+                    P, d, A, B, steps, me, flags, base, epoch, err, spin_limit, lds, S.bar, target);
             }
-            ++nbar;
-            const bool end_of_round = tile + 1 == S.ntiles;
-            const uint64_t tb = P.timing ? __builtin_amdgcn_s_memrealtime() : 0;
-            grid_barrier(S.bar, nbar, err, spin_limit, end_of_round, end_of_round, end_of_round);
-            if (P.timing) add_clock(P, me, kTimeBarrier, tb);
+            if (tile + 1 < S.ntiles) {
+                ++nbound;
+                tile_arrive(S.bar);
+            } else {
+                // The round's end: a full barrier that also makes B visible to
+                // every XCD (see above).
+                ++nbar;
+                const uint64_t tb = P.timing ? __builtin_amdgcn_s_memrealtime() : 0;
+                grid_barrier(S.bar, nbar, err, spin_limit, true, true, true);
+                if (P.timing) add_clock(P, me, kTimeBarrier, tb);
+            }
         }
         done += steps;
     }
