@@ -1160,10 +1160,12 @@ dtb_status plan3d_impl(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t col
             zb = (int)std::min<int64_t>(o.depth_D, depth);
         } else {
             // The block height with the least modelled launch time: taller blocks amortise the K-deep z ring,
-            // more blocks fill the compute units.  Measured: a launch streams best with several waves of
-            // workgroups queued per compute unit (512^3: 16-32 planes per block, 1600-3200 workgroups, beat
-            // 128-257 planes by 1.06-1.3x in FP64 and FP32), so blocks that leave fewer than four workgroups
-            // per compute unit are taken only when the grid is too shallow for more.
+            // more blocks fill the compute units.  Measured at 512^3: a launch bound by its memory traffic
+            // (FP64) streams best with several waves of workgroups queued per compute unit (46-48 planes per
+            // block, 1100-1200 workgroups, beat 64-128 planes by 1.08-1.09x), so for such launches blocks
+            // that leave fewer than four workgroups per compute unit are taken only when the grid is too
+            // shallow for more; a compute-bound one (FP32) is best with the fewest ring planes (64-128
+            // planes per block beat 18 by 1.12-1.13x).
             double best = 1e300;
             const int cap = o.max_wg > 0 ? std::min(o.max_wg, di.n_cu) : di.n_cu;
             const int64_t want = 4 * (int64_t)cap;
@@ -1172,9 +1174,10 @@ dtb_status plan3d_impl(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t col
                 const int nz = (int)((depth + z - 1) / z);
                 const int64_t nwg = (int64_t)ntiles * nz;
                 if (nwg > INT32_MAX / 2) continue;
-                if (deep_enough && (nwg < want || z < 4 * K)) continue;
+                bool bytes_bound = false;
                 const double t = stream3_launch_us((int)nwg, cap, ER, EC, z, K, (int)elem_size(dtype), depth,
-                                                   depth * rows * cols);
+                                                   depth * rows * cols, &bytes_bound);
+                if (bytes_bound && deep_enough && (nwg < want || z < 4 * K)) continue;
                 if (t < best) {
                     best = t;
                     zb = z;

@@ -593,13 +593,16 @@ bool split_axis3(int64_t n, int E, int K, std::vector<Span3>* out)
 }
 
 double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int elem_bytes, int64_t depth,
-                         int64_t interior_cells)
+                         int64_t interior_cells, bool* bytes_bound)
 {
-    // Measured on MI355X (512^3, one workgroup per compute unit): a launch streams at about 4.3 TB/s when
-    // every compute unit holds a workgroup, and each compute unit pulls its share, so fewer workgroups than
-    // compute units, or a last partial wave of them, leave bandwidth unused.  Bytes: every z-block loads its
-    // tile for its planes and a K-deep ring below and above; the owned cells are stored once.  The compute
-    // floor (a register-tile step per level per plane) rarely binds.
+    // Measured on MI355X (512^3, one workgroup per compute unit): a launch streams at about 4.3 TB/s (of the
+    // bytes below) when every compute unit holds a workgroup, and each compute unit pulls its share, so fewer
+    // workgroups than compute units, or a last partial wave of them, leave bandwidth unused.  Bytes: every
+    // z-block loads its tile for its planes and a K-deep ring below and above; the owned cells are stored
+    // once.  Compute: a workgroup takes about 130 ps per cell and level for every plane it streams (its
+    // K-plane rings included), whatever the precision (the FP64 and FP32 VALU rates are the same and the
+    // FP32 tile is twice as wide); the workgroups share the compute units.  FP64 (half the cells per plane)
+    // is bound by the bytes, FP32 by the compute, which favours deep z-blocks (fewer ring planes).
     const double bw = 4.3e6;  // bytes per microsecond
     const int64_t nz = (depth + zb - 1) / zb;
     const int64_t tiles = nz > 0 ? nwg / nz : nwg;
@@ -611,8 +614,9 @@ double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int e
     const double bytes = planes * tiles * ER * EC * elem_bytes + (double)interior_cells * elem_bytes;
     const double w = (double)nwg / std::max(1, n_cu);
     const double mem = bytes / bw * (std::ceil(w) / w);
-    const double cell = elem_bytes == 8 ? 70e-6 : 50e-6;
-    const double compute = std::ceil(w) * (zb + 2.0 * K) * ((double)ER * EC * cell * K + 0.3);
+    const double cell = 130e-6;  // microseconds per cell and level
+    const double compute = std::max(w, 1.0) * (zb + 2.0 * K) * ((double)ER * EC * cell * K + 0.3);
+    if (bytes_bound) *bytes_bound = mem >= compute;
     return std::max(mem, compute);
 }
 

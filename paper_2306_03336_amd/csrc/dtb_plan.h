@@ -209,9 +209,10 @@ bool split_axis3(int64_t n, int E, int K, std::vector<Span3>* out);
 
 // Model time (us) of one K-step streaming launch over nwg workgroups (tiles x
 // z-blocks of zb planes) of an ER x EC tile, one workgroup per compute unit,
-// for a grid of `depth` planes and `interior_cells` cells.
+// for a grid of `depth` planes and `interior_cells` cells.  *bytes_bound (if
+// given): the launch is bound by its memory traffic rather than its compute.
 double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int elem_bytes, int64_t depth,
-                         int64_t interior_cells);
+                         int64_t interior_cells, bool* bytes_bound = nullptr);
 
 // Exchange points run_epochs performs for a segment of `steps` steps.
 inline int exchanges_per_segment(int64_t steps, int k)

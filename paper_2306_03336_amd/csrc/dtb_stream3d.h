@@ -77,18 +77,43 @@ __device__ __forceinline__ T wave_shl1_3(T v)  // lane l gets lane l+1's value (
     return __builtin_amdgcn_update_dpp((T)0, v, 0x130, 0xf, 0xf, true);
 }
 
+// v in the lanes whose bit is set in `mask`, x in the others (one v_cndmask per 32 bits, the mask in SGPRs).
+__device__ __forceinline__ uint32_t keep_or32(uint64_t mask, uint32_t x, uint32_t v)
+{
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(v), "s"(mask));
+    return r;
+}
+__device__ __forceinline__ float keep_or(uint64_t mask, float x, float v)
+{
+    return __builtin_bit_cast(float, keep_or32(mask, __builtin_bit_cast(uint32_t, x), __builtin_bit_cast(uint32_t, v)));
+}
+__device__ __forceinline__ double keep_or(uint64_t mask, double x, double v)
+{
+    const uint64_t xb = __builtin_bit_cast(uint64_t, x), vb = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = keep_or32(mask, (uint32_t)xb, (uint32_t)vb);
+    const uint32_t hi = keep_or32(mask, (uint32_t)(xb >> 32), (uint32_t)(vb >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <typename T, int C, int R, int K, int WAVES>
 struct Stream3Geo {
     static constexpr int ER = WAVES * R;
     static constexpr int EC = 64 * C;
-    // LDS: [parity 2][level K][wave][top/bottom 2][EC]
-    static constexpr size_t kLdsBytes = (size_t)2 * K * WAVES * 2 * EC * sizeof(T);
+    // LDS: [parity 2][level K][wave][top/bottom 2][EC], then one row of zeros:
+    // what the first wave reads above its first row and the last wave below
+    // its last row (the tile's open edges; any value would do, since stale
+    // values there never reach the owned cells).
+    static constexpr size_t kEdgeElems = (size_t)2 * K * WAVES * 2 * EC;
+    static constexpr size_t kLdsBytes = (kEdgeElems + EC) * sizeof(T);
 };
 
 // The register pipeline of one workgroup.
 template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE, int PF>
 struct Stream3 {
     using G = Stream3Geo<T, C, R, K, WAVES>;
+    using Elem = T;
+    static constexpr int kC = C, kR = R, kK = K, kWaves = WAVES, kPF = PF;
     T win[K][3][R][C];   // level l's three most recent planes (slot: the plane's offset from the first, mod 3)
     T next[PF][R][C];    // the level-0 planes being loaded 1 .. PF iterations ahead
     Coef7<T> k;
@@ -96,8 +121,8 @@ struct Stream3 {
     int wave, lane;
     int g0;              // storage row of this wave's row 0
     int col0;            // storage column of this lane's slot 0
-    bool rowact[R];      // EDGE: row inside the interior
-    bool colact[C];      // EDGE: column inside the interior
+    bool rowact[R];      // EDGE: row inside the interior (uniform over the wave)
+    uint64_t colact[C];  // EDGE: the lanes whose column c is inside the interior (a wave-wide mask)
     bool rowown[R];      // row owned by this tile (stored)
     bool colown[C];      // column owned by this tile
     bool allown;         // all C columns owned
@@ -106,6 +131,7 @@ struct Stream3 {
     {
         return lds + ((size_t)(((parity * K + level) * WAVES + w) * 2 + bottom)) * G::EC;
     }
+    __device__ __forceinline__ const T* zero_row() const { return lds + G::kEdgeElems; }
 
     // Load plane z of the source (cells outside the stored grid read as 0).
     __device__ __forceinline__ void load_plane(const T* src, const Stream3Args& A, int z, T (&dst)[R][C])
@@ -136,6 +162,30 @@ struct Stream3 {
         }
     }
 
+    // Store the owned cells of plane q (level K) to the destination.
+    __device__ __forceinline__ void store_plane(T* dst, const Stream3Args& A, int q, const T (&out)[R][C])
+    {
+        T* plane = dst + (int64_t)q * A.plane_pitch;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!rowown[r]) continue;  // uniform over the wave
+            T* row = plane + (int64_t)(g0 + r) * A.pitch + col0;
+            if (allown) {
+                // every cell of the lane owned: one wide store of its C cells (aligned to the element only: the
+                // hardware takes unaligned wide accesses to global memory)
+                typedef T Vec __attribute__((ext_vector_type(C), aligned(sizeof(T))));
+                Vec v;
+#pragma unroll
+                for (int c = 0; c < C; ++c) v[c] = out[r][c];
+                *(Vec*)row = v;
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (colown[c]) row[c] = out[r][c];
+            }
+        }
+    }
+
     // Level `level` + 1 of plane q from level `level`'s planes q-1 (bw), q (cw), q+1 (aw): writes out.
     // above/below: the neighbouring waves' edge rows of plane q (zeros at the tile's first / last row).
     __device__ __forceinline__ void compute(const T (&bw)[R][C], const T (&cw)[R][C], const T (&aw)[R][C],
@@ -160,7 +210,8 @@ struct Stream3 {
                 const T S = r == 0 ? above[c] : cw[r - 1][c];
                 const T N = r == R - 1 ? below[c] : cw[r + 1][c];
                 T v = j3d7pt<FMA>(W, E, S, cw[r][c], N, bw[r][c], aw[r][c], k);
-                if constexpr (EDGE) v = (rowact[r] && colact[c]) ? v : cw[r][c];
+                // Cells outside the interior keep their value: one select by a scalar lane mask, no branch.
+                if constexpr (EDGE) v = keep_or(rowact[r] ? colact[c] : 0ull, cw[r][c], v);
                 out[r][c] = v;
             }
         }
@@ -170,6 +221,71 @@ struct Stream3 {
 // Slot of plane p0 + Um + u - l in a level's three-slot window (U a multiple of 3; u, l known at compile time
 // after unrolling).
 __host__ __device__ constexpr int stream_slot(int u, int l) { return ((u - l) % 3 + 3) % 3; }
+
+// U iterations of the streaming loop from iteration pb (see stream3_run).  FAST: every iteration of the
+// block has its level-0 plane and the plane PF ahead to load (pb + U + PF <= p_end), and every level
+// produces a plane of the interior inside its range (pb >= zo0 + K, so p - K >= zo0 >= 1, and p - 1 <
+// p_end - 1 <= depth): the conditions below are then all true and compiled out.
+template <bool FAST, int U, typename S3>
+__device__ __forceinline__ void stream3_block(S3& s, const Stream3Args& A, const typename S3::Elem* src,
+                                              typename S3::Elem* dst, int pb, int p_end, int p_stop, int zo0,
+                                              int zo1)
+{
+    using T = typename S3::Elem;
+    constexpr int C = S3::kC, R = S3::kR, K = S3::kK, WAVES = S3::kWaves, PF = S3::kPF;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int p = pb + u;
+        if constexpr (!FAST) {
+            if (p >= p_stop) break;
+        }
+        // Keep the scheduler from interleaving iterations of the branch-free block (its live ranges would no
+        // longer fit the register file).
+        __builtin_amdgcn_sched_barrier(0);
+        const int par = p & 1;
+        if (FAST || p < p_end) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < C; ++c) s.win[0][stream_slot(u, 0)][r][c] = s.next[u % PF][r][c];
+            if (FAST || p + PF < p_end) s.load_plane(src, A, p + PF, s.next[u % PF]);
+        }
+        // The centre planes' edge rows were published last iteration (the other LDS buffer).
+        __syncthreads();
+#pragma unroll
+        for (int l = 1; l <= K; ++l) {
+            const int q = p - l;
+            if constexpr (!FAST) {
+                const int lo = zo0 - K + l > 0 ? zo0 - K + l : 0;
+                const int hi = zo1 + K - l < A.depth + 2 ? zo1 + K - l : A.depth + 2;
+                if (q < lo || q >= hi) continue;
+            }
+            // The neighbouring waves' edge rows of plane q at level l - 1 (the zero row past the tile's
+            // first and last rows: a scalar choice of address, no per-lane select).
+            const T* ab = s.wave > 0 ? s.edge_row(par ^ 1, l - 1, s.wave - 1, 1) : s.zero_row();
+            const T* be = s.wave < WAVES - 1 ? s.edge_row(par ^ 1, l - 1, s.wave + 1, 0) : s.zero_row();
+            T above[C], below[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                above[c] = ab[c * 64 + s.lane];
+                below[c] = be[c * 64 + s.lane];
+            }
+            const bool interior = FAST || (q >= 1 && q <= A.depth);
+            if (l < K) {
+                s.compute(s.win[l - 1][stream_slot(u, l + 1)], s.win[l - 1][stream_slot(u, l)],
+                          s.win[l - 1][stream_slot(u, l - 1)], above, below, interior, s.win[l][stream_slot(u, l)]);
+            } else {
+                T out[R][C];
+                s.compute(s.win[l - 1][stream_slot(u, l + 1)], s.win[l - 1][stream_slot(u, l)],
+                          s.win[l - 1][stream_slot(u, l - 1)], above, below, interior, out);
+                s.store_plane(dst, A, q, out);
+            }
+        }
+        // Publish every level's newest plane (the centre planes of the next iteration).
+#pragma unroll
+        for (int l = 0; l < K; ++l) s.publish(par, l, s.win[l][stream_slot(u, l)]);
+    }
+}
 
 // One K-step launch of one workgroup: tile `d`, owned planes [zo0, zo1).
 // PF: planes loaded ahead (1 or 2).  Measured at 512^3: FP32 gains from two (519 -> 537 GCells/s), FP64,
@@ -189,7 +305,7 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
 #pragma unroll
     for (int r = 0; r < R; ++r) s.rowact[r] = s.g0 + r >= 1 && s.g0 + r <= A.rows;
 #pragma unroll
-    for (int c = 0; c < C; ++c) s.colact[c] = s.col0 + c >= 1 && s.col0 + c <= A.cols;
+    for (int c = 0; c < C; ++c) s.colact[c] = __builtin_amdgcn_ballot_w64(s.col0 + c >= 1 && s.col0 + c <= A.cols);
 #pragma unroll
     for (int r = 0; r < R; ++r) s.rowown[r] = s.g0 + r >= d.own_r0 && s.g0 + r < d.own_r1;
 #pragma unroll
@@ -205,75 +321,22 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
     if constexpr (PF == 2) {
         if (p0 + 1 < p_end) s.load_plane(src, A, p0 + 1, s.next[1]);
     }
+    // The zero row (read by the outermost waves) is visible after the first
+    // barrier of the loop, before any read.
+    using G = Stream3Geo<T, C, R, K, WAVES>;
+    for (int i = threadIdx.x; i < G::EC; i += WAVES * 64) lds[G::kEdgeElems + i] = T(0);
     // Iteration p: level 0 takes plane p, level l = 1 .. K produces plane p - l (when it has one); the
     // last owned plane, zo1 - 1, leaves level K at iteration zo1 - 1 + K.
-    // Unrolled by three (six with two prefetch buffers): window slots repeat every three planes.
+    // Unrolled by three (six with two prefetch buffers): window slots repeat every three planes.  A block of
+    // iterations in which every one loads its plane and the plane PF ahead, and every level produces an
+    // interior plane, runs without any of the per-iteration conditions (stream3_block<true>): no branches,
+    // so the window stays in place (no register copies at branch joins) and the loads are counted exactly.
     constexpr int U = PF == 2 ? 6 : 3;
     const int p_stop = zo1 + K;
-    for (int pb = p0; pb < p_stop; pb += U) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = pb + u;
-            if (p >= p_stop) break;
-            const int par = p & 1;
-            if (p < p_end) {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int c = 0; c < C; ++c) s.win[0][stream_slot(u, 0)][r][c] = s.next[u % PF][r][c];
-                if (p + PF < p_end) s.load_plane(src, A, p + PF, s.next[u % PF]);
-            }
-            // The centre planes' edge rows were published last iteration (the other LDS buffer).
-            __syncthreads();
-#pragma unroll
-            for (int l = 1; l <= K; ++l) {
-                const int q = p - l;
-                const int lo = zo0 - K + l > 0 ? zo0 - K + l : 0;
-                const int hi = zo1 + K - l < A.depth + 2 ? zo1 + K - l : A.depth + 2;
-                if (q < lo || q >= hi) continue;
-                T above[C], below[C];
-                const T* ab = s.edge_row(par ^ 1, l - 1, s.wave > 0 ? s.wave - 1 : 0, 1);
-                const T* be = s.edge_row(par ^ 1, l - 1, s.wave < WAVES - 1 ? s.wave + 1 : 0, 0);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    above[c] = s.wave > 0 ? ab[c * 64 + s.lane] : T(0);
-                    below[c] = s.wave < WAVES - 1 ? be[c * 64 + s.lane] : T(0);
-                }
-                const bool interior = q >= 1 && q <= A.depth;
-                if (l < K) {
-                    s.compute(s.win[l - 1][stream_slot(u, l + 1)], s.win[l - 1][stream_slot(u, l)],
-                              s.win[l - 1][stream_slot(u, l - 1)], above, below, interior,
-                              s.win[l][stream_slot(u, l)]);
-                } else {
-                    T out[R][C];
-                    s.compute(s.win[l - 1][stream_slot(u, l + 1)], s.win[l - 1][stream_slot(u, l)],
-                              s.win[l - 1][stream_slot(u, l - 1)], above, below, interior, out);
-                    T* plane = dst + (int64_t)q * A.plane_pitch;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        if (!s.rowown[r]) continue;  // uniform over the wave
-                        T* row = plane + (int64_t)(s.g0 + r) * A.pitch + s.col0;
-                        if (s.allown) {
-                            // every cell of the lane owned: one wide store of its C cells (aligned to the
-                            // element only: the hardware takes unaligned wide accesses to global memory)
-                            typedef T Vec __attribute__((ext_vector_type(C), aligned(sizeof(T))));
-                            Vec v;
-#pragma unroll
-                            for (int c = 0; c < C; ++c) v[c] = out[r][c];
-                            *(Vec*)row = v;
-                        } else {
-#pragma unroll
-                            for (int c = 0; c < C; ++c)
-                                if (s.colown[c]) row[c] = out[r][c];
-                        }
-                    }
-                }
-            }
-            // Publish every level's newest plane (the centre planes of the next iteration).
-#pragma unroll
-            for (int l = 0; l < K; ++l) s.publish(par, l, s.win[l][stream_slot(u, l)]);
-        }
-    }
+    int pb = p0;
+    for (; pb < p_stop && pb < zo0 + K; pb += U) stream3_block<false, U>(s, A, src, dst, pb, p_end, p_stop, zo0, zo1);
+    for (; pb + U + PF <= p_end; pb += U) stream3_block<true, U>(s, A, src, dst, pb, p_end, p_stop, zo0, zo1);
+    for (; pb < p_stop; pb += U) stream3_block<false, U>(s, A, src, dst, pb, p_end, p_stop, zo0, zo1);
 }
 
 // The K-step streaming kernel.  Workgroup b: tile b % ntiles, z-block b / ntiles.

@@ -76,6 +76,26 @@ def test_3d_stream_exact_bitwise(shape, dtype):
         assert np.array_equal(got, ref), (shape, K, T, zb, float(np.max(np.abs(got.astype(float) - ref))))
 
 
+@pytest.mark.parametrize("shape", [(64, 40, 130), (50, 33, 300)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_3d_stream_exact_bitwise_deep_blocks(shape, dtype):
+    """Deep z-blocks, so that most iterations of a workgroup run the streaming loop's branch-free steady state
+    (every plane loaded ahead, every level producing an interior plane); shallow ones and the ends of the grid
+    take the general form.  Both must equal the oracle bit for bit."""
+    depth, rows, cols = shape
+    npd = np.float64 if dtype == "f64" else np.float32
+    ref_fn = oracle.j3d7pt_f64 if dtype == "f64" else oracle.j3d7pt_f32
+    rng = np.random.default_rng(depth * 7 + rows * 3 + cols)
+    coeffs = inputs.weights7(rng)
+    u = _random_shell(inputs.uniform_grid3(depth, rows, cols, rng), rng).astype(npd)
+    for K, T, zb in [(3, 7, depth), (3, 4, 30), (2, 5, 25), (1, 3, depth), (3, 9, 17)]:
+        _say("3d exact deep", dtype, shape, "K", K, "T", T, "zb", zb)
+        got, desc = _run(u, coeffs, T, dtype=npd, path=dtb.PATH_STREAM3D, ghost_k=K, depth_D=zb, exact=True)
+        assert desc["path"] == dtb.PATH_STREAM3D and desc["ghost_k"] == K and desc["depth_D"] == zb, desc
+        ref = ref_fn(u, coeffs, T)
+        assert np.array_equal(got, ref), (shape, K, T, zb, float(np.max(np.abs(got.astype(float) - ref))))
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("shape_pitch", [(3, 4, 5, 8, 0), (9, 40, 130, 133, 42 * 133 + 5), (17, 33, 300, 302, 0)],
                          ids=lambda s: "x".join(map(str, s)))
