@@ -840,20 +840,22 @@ __device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t n, int* err
     if (acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-// Split-phase barrier between two big tiles of one round of the sweep.  The
+// Split-phase barrier between two big tiles of one round of a sweep.  The
 // only thing it orders is the reuse of the exchange buffers: no workgroup may
 // store the strips of big tile m while another one may still read strips of
 // big tile m - 1 (tile m reads buffer A, which no one writes in this round,
 // and stores its own cells of buffer B, so nothing else needs it).  Every
-// workgroup adds one to a single counter when it is done with a big tile
-// (its ring loads have all returned by then), and before it works on the next
-// big tile of the round it waits until the counter has reached
-// nwg * (boundaries so far, counted over the whole launch).  The first time
-// the counter reaches nwg * m every workgroup has arrived exactly m times,
-// since none arrives an (m + 1)-th time before it has waited for nwg * m.
-// The wait is read once before the tile load is issued and checked after it
-// (the loads hide the round trip); only if the count is short does thread 0
-// keep polling (bounded, as in grid_barrier).
+// workgroup signals when it is done with a big tile (its ring loads have all
+// returned by then) and, before its first strip store in the next big tile of
+// the round, waits for the others' signals (n words, each to reach `target`).
+// The tile-serial sweep counts arrivals in one word (n = 1,
+// target nwg * m: the first time the count reaches nwg * m every workgroup has
+// arrived exactly m times, since none arrives an (m + 1)-th time before it has
+// waited for nwg * m); a swept job of the batched kernel uses its members'
+// epoch flags (n = group size, target the boundary's epoch; flags only grow).
+// The words are read once before the tile load is issued and checked after it
+// (the loads hide the round trip); only a word that is short is polled again
+// (bounded, as in grid_barrier).
 __device__ __forceinline__ void tile_arrive(uint32_t* bar)
 {
     if (threadIdx.x == 0)
@@ -861,18 +863,25 @@ __device__ __forceinline__ void tile_arrive(uint32_t* bar)
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t tile_count_peek(uint32_t* bar)
+// GATE 1: one word (the sweep's counter), read by thread 0; GATE 2: the n
+// words words[i * kFlagStride] (a batched job's member flags), thread i
+// reading word i.  Threads without a word see the target.
+template <int GATE>
+__device__ __forceinline__ uint32_t gate_peek(const uint32_t* words, uint32_t target, int n)
 {
-    return threadIdx.x == 0 ? __hip_atomic_load(bar + (size_t)kTileCountSlot * kFlagStride, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT)
-                            : 0u;
+    const int nw = GATE == 1 ? 1 : n;
+    return (int)threadIdx.x < nw ? __hip_atomic_load(words + (size_t)threadIdx.x * kFlagStride, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : target;
 }
 
-__device__ __forceinline__ void tile_wait(uint32_t* bar, uint32_t seen, uint32_t target, int* err,
+template <int GATE>
+__device__ __forceinline__ void gate_wait(uint32_t* words, uint32_t target, int n, uint32_t seen, int* err,
                                           uint32_t spin_limit)
 {
-    if (threadIdx.x == 0 && !reached(seen, target))
-        spin_until(bar + (size_t)kTileCountSlot * kFlagStride, target, err, 2, spin_limit);
+    const int nw = GATE == 1 ? 1 : n;
+    if ((int)threadIdx.x < nw && !reached(seen, target))
+        spin_until(words + (size_t)threadIdx.x * kFlagStride, target, err, GATE == 1 ? 2 : 4, spin_limit);
     __syncthreads();
 }
 
@@ -1155,24 +1164,25 @@ __device__ __forceinline__ void load_tile(Tl& t, const ProbDesc& P, const WgDesc
 // and written with device-scope accesses (other XCDs wrote / will read them
 // inside the same launch).
 template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, bool HALO_ROWS, bool SWEEP,
-          bool STAGED = true, int PTS = 5>
+          bool STAGED = true, int PTS = 5, int GATE = 0>
 __device__ __forceinline__ void run_segment(const ProbDesc& P, const WgDesc& d, const T* src, T* dst, int64_t steps,
                                             int me, uint32_t* flags, uint32_t base, uint32_t& epoch, int* err,
-                                            uint32_t spin_limit, char* lds, uint32_t* tile_bar = nullptr,
-                                            uint32_t tile_target = 0)
+                                            uint32_t spin_limit, char* lds, uint32_t* gate_words = nullptr,
+                                            uint32_t gate_target = 0, int gate_n = 0)
 {
     using Tl = Tile<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, PTS>;
     Tl t;
     const bool timing = P.timing != nullptr;  // DTB_DEBUG_TIMING (uniform branch)
     uint64_t t0 = timing ? __builtin_amdgcn_s_memrealtime() : 0;
-    // tile_target != 0: the split-phase barrier of the sweep (tile_wait) must
-    // have been passed before this segment's first strip store.
-    const uint32_t seen = tile_target != 0 ? tile_count_peek(tile_bar) : 0u;
+    // gate_words != null (GATE 1 or 2): the split-phase barrier between big
+    // tiles must have been passed before this segment's first strip store.
+    const bool gated = GATE != 0 && gate_words != nullptr;
+    const uint32_t seen = gated ? gate_peek<GATE>(gate_words, gate_target, gate_n) : 0u;
     load_tile<SWEEP>(t, P, d, src, lds);
     if (timing) add_clock(P, me, kTimeLoad, t0);
-    if (tile_target != 0) {
+    if (gated) {
         if (timing) t0 = __builtin_amdgcn_s_memrealtime();
-        tile_wait(tile_bar, seen, tile_target, err, spin_limit);
+        gate_wait<GATE>(gate_words, gate_target, gate_n, seen, err, spin_limit);
         if (timing) add_clock(P, me, kTimeBarrier, t0);
     }
     run_epochs<HALO_ROWS, STAGED>(t, P, d, steps, me, flags, base, epoch, err, spin_limit);
@@ -1295,7 +1305,7 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepAr
     // own valid part of B), so the barrier between two of them only keeps the
     // next tile's exchanges from overwriting strips of this one that a slower
     // workgroup may still read: a split-phase barrier (tile_arrive, then
-    // tile_wait after the next tile's load) that does not wait for this
+    // gate_wait after the next tile's load) that does not wait for this
     // tile's stores to B, which drain while the next tile loads.  B is read in
     // the next round only: the round's last barrier waits for the stores,
     // makes them visible to every XCD (agent-scope release) and, past the
@@ -1310,19 +1320,20 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepAr
         for (int tile = 0; tile < S.ntiles; ++tile) {
             const WgDesc& d = table[(size_t)tile * S.nwg + me];
             // Past the first big tile of a round, wait for every workgroup to
-            // be done with the previous one (tile_wait) before storing strips.
-            const uint32_t target = tile > 0 ? nbound * gridDim.x : 0u;
+            // be done with the previous one before storing strips.
+            uint32_t* const gw = tile > 0 ? S.bar + (size_t)kTileCountSlot * kFlagStride : nullptr;
+            const uint32_t target = nbound * gridDim.x;
             if (d.own_r0 == d.own_r1) {
                 // Idle for this tile: keep the epoch count in step with the others.
                 const int64_t per = (steps + P.k - 1) / P.k - 1;
                 epoch += per > 0 ? (uint32_t)per : 1u;
-                if (target != 0) tile_wait(S.bar, tile_count_peek(S.bar), target, err, spin_limit);
+                if (gw != nullptr) gate_wait<1>(gw, target, 1, gate_peek<1>(gw, target, 1), err, spin_limit);
             } else if (halo_varies<T, C, R, WAVES, COLMASK, PTS>(P, d)) {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false, true, PTS>(
-                    P, d, A, B, steps, me, flags, base, epoch, err, spin_limit, lds, S.bar, target);
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, true, false, true, PTS, 1>(
+                    P, d, A, B, steps, me, flags, base, epoch, err, spin_limit, lds, gw, target);
             } else {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false, true, PTS>(
-                    P, d, A, B, steps, me, flags, base, epoch, err, spin_limit, lds, S.bar, target);
+                run_segment<T, C, R, WAVES, FMA, COLMASK, ROWCHECK, false, false, true, PTS, 1>(
+                    P, d, A, B, steps, me, flags, base, epoch, err, spin_limit, lds, gw, target);
             }
             if (tile + 1 < S.ntiles) {
                 ++nbound;
@@ -1418,6 +1429,12 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
     ++epoch;
     group_point(flags, J.flag_base, J.g, local, base + epoch, err, spin_limit);
     int64_t done = 0;
+    // As in the tile-serial sweep: the big tiles of a round are separated by a
+    // split-phase barrier on the members' epoch flags (a member raises its flag
+    // when done with a tile, and waits for everyone's before its first strip
+    // store in the next one); the round's end is a full group barrier that
+    // releases the plain stores of B and, past it, acquires them, so that A is
+    // read with plain loads.
     for (int round = 0; round < J.nrounds; ++round) {
         const T* A = (round & 1) ? ws : grid;
         T* B = (round & 1) ? grid : ws;
@@ -1425,18 +1442,29 @@ __device__ __forceinline__ void run_job(const ProbDesc& P, const JobDesc& J, con
         const int64_t steps = left < J.D ? left : J.D;
         for (int tile = 0; tile < J.ntiles; ++tile) {
             const WgDesc& d = table[J.table_off + (size_t)tile * J.g + local];
+            uint32_t* const gw = tile > 0 ? flags + (size_t)J.flag_base * kFlagStride : nullptr;
+            const uint32_t target = base + epoch;  // the epoch every member raised at the end of the last tile
             if (d.own_r0 == d.own_r1) {
                 const int64_t per = (steps + P.k - 1) / P.k - 1;
                 epoch += per > 0 ? (uint32_t)per : 1u;
+                if (gw != nullptr) gate_wait<2>(gw, target, J.g, gate_peek<2>(gw, target, J.g), err, spin_limit);
             } else if (halo_varies<T, C, R, WAVES, COLMASK>(P, d)) {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, true, true, true, true>(P, d, A, B, steps, me, flags, base,
-                                                                             epoch, err, spin_limit, lds);
+                run_segment<T, C, R, WAVES, FMA, COLMASK, true, true, false, true, 5, 2>(
+                    P, d, A, B, steps, me, flags, base, epoch, err, spin_limit, lds, gw, target, J.g);
             } else {
-                run_segment<T, C, R, WAVES, FMA, COLMASK, true, false, true, true>(P, d, A, B, steps, me, flags, base,
-                                                                              epoch, err, spin_limit, lds);
+                run_segment<T, C, R, WAVES, FMA, COLMASK, true, false, false, true, 5, 2>(
+                    P, d, A, B, steps, me, flags, base, epoch, err, spin_limit, lds, gw, target, J.g);
             }
             ++epoch;
-            group_point(flags, J.flag_base, J.g, local, base + epoch, err, spin_limit, true);
+            if (tile + 1 < J.ntiles) {
+                // Arrive: this member is done with the tile (its ring loads have returned).
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(flags + (size_t)me * kFlagStride, base + epoch, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                group_point(flags, J.flag_base, J.g, local, base + epoch, err, spin_limit, true);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
         }
         done += steps;
     }
