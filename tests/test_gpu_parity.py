@@ -535,6 +535,33 @@ def test_watchdog_reports_timeout_and_drains():
     assert oracle.rel_max_err(got, oracle.j2d5pt_f64(u, inputs.EQUAL_WEIGHTS, 10)) <= TOL_F64
 
 
+def test_sweep_watchdog_reports_timeout_and_drains():
+    """The tile-serial sweep's bounded waits (exchange flags, the split-phase barrier between big tiles, the
+    device barrier at the end of a round) cut to a few polls: the run still ends, and dtb_plan_check reports
+    DTB_ERR_TIMEOUT (or, if nobody had to wait, the result is right)."""
+    rows, cols, T = 3000, 3000, 40
+    u = inputs.uniform_grid(rows, cols, 94)
+    g = _dev(u)
+    plan = dtb.plan_for(g, T, path=dtb.PATH_SWEEP, ghost_k=4, depth_D=16, rows_per_lane=8,
+                        debug=dtb.DEBUG_TINY_SPIN)
+    d = plan.describe()
+    assert d["path"] == dtb.PATH_SWEEP and d["big_tiles"] >= 2, d
+    _say("sweep watchdog", d["big_tiles"], "big tiles")
+    plan.run(g, inputs.EQUAL_WEIGHTS, T)
+    try:
+        plan.check()
+        timed_out = False
+    except dtb.DtbError as e:
+        assert e.status == -6
+        timed_out = True
+    if not timed_out:
+        assert oracle.rel_max_err(g.cpu().numpy(), oracle.j2d5pt_f64(u, inputs.EQUAL_WEIGHTS, T)) <= TOL_F64
+    plan.destroy()
+    # a normal sweep plan afterwards works
+    got, _ = _run_plan(u, inputs.EQUAL_WEIGHTS, 20, path=dtb.PATH_SWEEP, ghost_k=4, depth_D=16, rows_per_lane=8)
+    assert oracle.rel_max_err(got, oracle.j2d5pt_f64(u, inputs.EQUAL_WEIGHTS, 20)) <= TOL_F64
+
+
 def test_tuned_plan_is_correct():
     rows, cols, T = 1500, 1700, 120
     coeffs = inputs.dirichlet_weights(93)
