@@ -224,8 +224,9 @@ __host__ __device__ constexpr int stream_slot(int u, int l) { return ((u - l) % 
 
 // U iterations of the streaming loop from iteration pb (see stream3_run).  FAST: every iteration of the
 // block has its level-0 plane and the plane PF ahead to load (pb + U + PF <= p_end), and every level
-// produces a plane of the interior inside its range (pb >= zo0 + K, so p - K >= zo0 >= 1, and p - 1 <
-// p_end - 1 <= depth): the conditions below are then all true and compiled out.
+// produces a plane of the interior inside its range (pb >= zo0 + K, so p - K >= zo0 >= 1; and p <= p_end -
+// PF - 1 with p_end <= depth + 2, so p - 1 <= depth - 1): the conditions below are then all true and
+// compiled out.
 template <bool FAST, int U, typename S3>
 __device__ __forceinline__ void stream3_block(S3& s, const Stream3Args& A, const typename S3::Elem* src,
                                               typename S3::Elem* dst, int pb, int p_end, int p_stop, int zo0,
@@ -327,10 +328,12 @@ __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Des
     for (int i = threadIdx.x; i < G::EC; i += WAVES * 64) lds[G::kEdgeElems + i] = T(0);
     // Iteration p: level 0 takes plane p, level l = 1 .. K produces plane p - l (when it has one); the
     // last owned plane, zo1 - 1, leaves level K at iteration zo1 - 1 + K.
-    // Unrolled by three (six with two prefetch buffers): window slots repeat every three planes.  A block of
+    // Unrolled by three (six with two prefetch buffers): window slots repeat every three planes.  Blocks of
     // iterations in which every one loads its plane and the plane PF ahead, and every level produces an
-    // interior plane, runs without any of the per-iteration conditions (stream3_block<true>): no branches,
+    // interior plane, run without any of the per-iteration conditions (stream3_block<true>): no branches,
     // so the window stays in place (no register copies at branch joins) and the loads are counted exactly.
+    // They form one run in the middle of the z-block (the conditions hold from pb = zo0 + K until
+    // pb + U + PF > p_end), with the general form before and after it, each in a loop of its own.
     constexpr int U = PF == 2 ? 6 : 3;
     const int p_stop = zo1 + K;
     int pb = p0;
