@@ -61,6 +61,16 @@ int32_t dtb_test_sweep(int64_t rows, int64_t cols, int32_t rows_per_lane, int32_
  */
 int32_t dtb_test_split3(int64_t n, int32_t E, int32_t K, int32_t* out, int32_t max_spans);
 
+/*
+ * The z-block height (planes per block) the j3d7pt planner (dtb_plan3d)
+ * picks when the caller leaves it open, for ntiles column tiles of
+ * ext_rows x ext_cols cells, K steps per launch, elem_bytes 8 (FP64) or 4
+ * (FP32), a grid of `depth` planes and `interior_cells` interior cells, on
+ * n_cu compute units.  Returns -1 if an argument is invalid.  Host only.
+ */
+int32_t dtb_test_zblock(int64_t ntiles, int32_t ext_rows, int32_t ext_cols, int32_t K, int32_t elem_bytes,
+                        int64_t depth, int64_t interior_cells, int32_t n_cu);
+
 #define DTB_TEST_BATCH_STRIDE 13
 
 /*

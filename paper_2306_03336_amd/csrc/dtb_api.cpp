@@ -1159,30 +1159,8 @@ dtb_status plan3d_impl(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t col
         if (o.depth_D > 0) {
             zb = (int)std::min<int64_t>(o.depth_D, depth);
         } else {
-            // The block height with the least modelled launch time: taller blocks amortise the K-deep z ring,
-            // more blocks fill the compute units.  Measured at 512^3: a launch bound by its memory traffic
-            // (FP64) streams best with several waves of workgroups queued per compute unit (46-48 planes per
-            // block, 1100-1200 workgroups, beat 64-128 planes by 1.08-1.09x), so for such launches blocks
-            // that leave fewer than four workgroups per compute unit are taken only when the grid is too
-            // shallow for more; a compute-bound one (FP32) is best with the fewest ring planes (64-128
-            // planes per block beat 18 by 1.12-1.13x).
-            double best = 1e300;
             const int cap = o.max_wg > 0 ? std::min(o.max_wg, di.n_cu) : di.n_cu;
-            const int64_t want = 4 * (int64_t)cap;
-            const bool deep_enough = (int64_t)ntiles * ((depth + 4 * K - 1) / (4 * K)) >= want;
-            for (int z = 1; z <= depth; z = z < 16 ? z + 1 : z + z / 8) {
-                const int nz = (int)((depth + z - 1) / z);
-                const int64_t nwg = (int64_t)ntiles * nz;
-                if (nwg > INT32_MAX / 2) continue;
-                bool bytes_bound = false;
-                const double t = stream3_launch_us((int)nwg, cap, ER, EC, z, K, (int)elem_size(dtype), depth,
-                                                   depth * rows * cols, &bytes_bound);
-                if (bytes_bound && deep_enough && (nwg < want || z < 4 * K)) continue;
-                if (t < best) {
-                    best = t;
-                    zb = z;
-                }
-            }
+            zb = choose_zblock(ntiles, ER, EC, K, (int)elem_size(dtype), depth, depth * rows * cols, cap);
         }
         const int64_t nzb = (depth + zb - 1) / zb;
         if ((int64_t)ntiles * nzb > INT32_MAX / 2) return DTB_ERR_UNSUPPORTED;
@@ -1558,6 +1536,15 @@ int32_t dtb_test_split3(int64_t n, int32_t E, int32_t K, int32_t* out, int32_t m
         out[3 * i + 2] = spans[i].own1;
     }
     return ns;
+}
+
+int32_t dtb_test_zblock(int64_t ntiles, int32_t ext_rows, int32_t ext_cols, int32_t K, int32_t elem_bytes,
+                        int64_t depth, int64_t interior_cells, int32_t n_cu)
+{
+    if (ntiles < 1 || ext_rows < 1 || ext_cols < 1 || K < 1 || (elem_bytes != 4 && elem_bytes != 8) || depth < 1 ||
+        interior_cells < 1 || n_cu < 1)
+        return -1;
+    return choose_zblock(ntiles, ext_rows, ext_cols, K, elem_bytes, depth, interior_cells, n_cu);
 }
 
 }  // extern "C"

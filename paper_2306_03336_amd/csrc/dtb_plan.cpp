@@ -620,5 +620,33 @@ double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int e
     return std::max(mem, compute);
 }
 
-}  // namespace dtb
+int choose_zblock(int64_t ntiles, int ER, int EC, int K, int elem_bytes, int64_t depth, int64_t interior_cells,
+                  int n_cu)
+{
+    // The block height with the least modelled launch time: taller blocks amortise the K-deep z ring, more
+    // blocks fill the compute units.  Measured at 512^3: a launch bound by its memory traffic (FP64) streams
+    // best with several waves of workgroups queued per compute unit (46-48 planes per block, 1100-1200
+    // workgroups, beat 64-128 planes by 1.08-1.09x), so for such launches blocks that leave fewer than four
+    // workgroups per compute unit are taken only when the grid is too shallow for more; a compute-bound one
+    // (FP32) is best with the fewest ring planes (64-128 planes per block beat 18 by 1.12-1.13x).
+    double best = 1e300;
+    int zb = 1;
+    const int64_t want = 4 * (int64_t)n_cu;
+    const bool deep_enough = ntiles * ((depth + 4 * K - 1) / (4 * K)) >= want;
+    for (int z = 1; z <= depth; z = z < 16 ? z + 1 : z + z / 8) {
+        const int64_t nz = (depth + z - 1) / z;
+        const int64_t nwg = ntiles * nz;
+        if (nwg > INT32_MAX / 2) continue;
+        bool bytes_bound = false;
+        const double t = stream3_launch_us((int)nwg, n_cu, ER, EC, z, K, elem_bytes, depth, interior_cells,
+                                           &bytes_bound);
+        if (bytes_bound && deep_enough && (nwg < want || z < 4 * K)) continue;
+        if (t < best) {
+            best = t;
+            zb = z;
+        }
+    }
+    return zb;
+}
 
+}  // namespace dtb

@@ -214,6 +214,13 @@ bool split_axis3(int64_t n, int E, int K, std::vector<Span3>* out);
 double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int elem_bytes, int64_t depth,
                          int64_t interior_cells, bool* bytes_bound = nullptr);
 
+// The z-block height (planes) of a j3d7pt streaming plan with the least
+// modelled launch time, for ntiles column tiles of ER x EC cells, K steps per
+// launch, a grid of `depth` planes and `interior_cells` cells, on n_cu compute
+// units (stream3_launch_us; see its definition for the measured rule).
+int choose_zblock(int64_t ntiles, int ER, int EC, int K, int elem_bytes, int64_t depth, int64_t interior_cells,
+                  int n_cu);
+
 // Exchange points run_epochs performs for a segment of `steps` steps.
 inline int exchanges_per_segment(int64_t steps, int k)
 {

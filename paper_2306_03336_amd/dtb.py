@@ -65,7 +65,7 @@ class Problem(ctypes.Structure):
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
            "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep",
            "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing", "dtb_probe", "dtb_run_noalloc", "dtb_plan3d",
-           "dtb_run3d_plan", "dtb_test_split3")
+           "dtb_run3d_plan", "dtb_test_split3", "dtb_test_zblock")
 TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
@@ -93,6 +93,9 @@ def load():
     lib.dtb_test_split3.restype = ctypes.c_int32
     lib.dtb_test_split3.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.c_int32]
+    lib.dtb_test_zblock.restype = ctypes.c_int32
+    lib.dtb_test_zblock.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
     lib.dtb_run.restype = ctypes.c_int
     lib.dtb_run.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int, P]
     lib.dtb_run_batched.restype = ctypes.c_int
@@ -354,6 +357,13 @@ def test_split3(n: int, E: int, K: int):
     buf = (ctypes.c_int32 * (3 * m))()
     assert lib.dtb_test_split3(n, E, K, buf, m) == m
     return [tuple(buf[3 * i:3 * i + 3]) for i in range(m)]
+
+
+def test_zblock(ntiles: int, ext_rows: int, ext_cols: int, K: int, elem_bytes: int, depth: int,
+                interior_cells: int, n_cu: int = 256):
+    """The z-block height the 3-D streaming planner picks, without a GPU (or None for invalid arguments)."""
+    z = load().dtb_test_zblock(ntiles, ext_rows, ext_cols, K, elem_bytes, depth, interior_cells, n_cu)
+    return None if z < 0 else z
 
 
 def test_sweep(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, waves: int, k: int, D: int,
