@@ -930,7 +930,9 @@ dtb_status make_batch(const dtb_problem* problems, int32_t count, int device, Ba
     const void* kfn = batched_kernel(b->insts, &b->ninst);
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, 8 * kWaveSize, 0) != hipSuccess) return DTB_ERR_HIP;
-    const int nslots = std::min(occ, 1) * di.n_cu;
+    // One slot per compute unit; at most one per thread of a workgroup, since a swept job's members wait for
+    // each other with one thread per member flag.
+    const int nslots = std::min(std::min(occ, 1) * di.n_cu, 8 * kWaveSize);
     if (nslots < 1) return DTB_ERR_NOT_CORESIDENT;
     std::vector<BatchSpec> specs(count);
     for (int i = 0; i < count; ++i) {

@@ -865,7 +865,9 @@ __device__ __forceinline__ void tile_arrive(uint32_t* bar)
 
 // GATE 1: one word (the sweep's counter), read by thread 0; GATE 2: the n
 // words words[i * kFlagStride] (a batched job's member flags), thread i
-// reading word i.  Threads without a word see the target.
+// reading word i, so n must not exceed the workgroup size (a batched job has
+// at most one member per compute unit, 256, against 512 threads).  Threads
+// without a word see the target.
 template <int GATE>
 __device__ __forceinline__ uint32_t gate_peek(const uint32_t* words, uint32_t target, int n)
 {
