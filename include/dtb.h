@@ -226,8 +226,9 @@ dtb_status dtb_plan_check(dtb_plan_t plan, void* stream);
  * the ticks spent moving the published strips from registers to LDS and the
  * loaded ring from the buffer to LDS (not counted in the publishing and
  * loading figures); then ticks spent loading extended tiles, storing owned
- * cells, and (tile-serial sweep) in the device-wide barrier between big tiles
- * (these three outside the total).  DTB_ERR_NOT_PLANNED if the plan has no
+ * cells, and (tile-serial sweep) in the barriers between big tiles (the
+ * split-phase wait inside a round, the device-wide barrier at its end; these
+ * three outside the total).  DTB_ERR_NOT_PLANNED if the plan has no
  * clocks.
  */
 dtb_status dtb_plan_timing(dtb_plan_t plan, uint64_t* out, int32_t n, void* stream);

@@ -1291,8 +1291,9 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_ovl(ProbDesc P, const WgDesc*
 // The tile-serial sweep (Sections 1, 3.1, 3.3, Figure 1): rounds of D steps;
 // in every round the big tiles run one after another on the whole chip, each
 // reading its computed region (valid part + D ring) from buffer A and writing
-// its valid part to buffer B; a device-wide barrier separates tiles.  Round r
-// reads bufs[r & 1] and writes bufs[(r + 1) & 1]; bufs[0] is the grid.
+// its valid part to buffer B; a split-phase barrier separates the big tiles
+// of a round, a device-wide barrier the rounds.  Round r reads bufs[r & 1]
+// and writes bufs[(r + 1) & 1]; bufs[0] is the grid.
 template <typename T, int C, int R, int WAVES, bool FMA, bool COLMASK, bool ROWCHECK, int PTS = 5>
 __global__ __launch_bounds__(WAVES * 64, 2) void k_dtb_sweep(ProbDesc P, SweepArgs S, const WgDesc* __restrict__ table,
                                                           uint32_t* flags, int* err, uint32_t spin_limit)
