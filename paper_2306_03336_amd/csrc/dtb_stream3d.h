@@ -289,8 +289,9 @@ __device__ __forceinline__ void stream3_block(S3& s, const Stream3Args& A, const
 }
 
 // One K-step launch of one workgroup: tile `d`, owned planes [zo0, zo1).
-// PF: planes loaded ahead (1 or 2).  Measured at 512^3: FP32 gains from two (519 -> 537 GCells/s), FP64,
-// whose launch is bound by HBM traffic, loses (518 -> 485) to the extra registers.
+// PF: planes loaded ahead (1 or 2).  Measured at 512^3 with the branch-free steady state: swapping the
+// depths (FP64 two, FP32 one) lost in both (FP64 682 -> 678, FP32 893 -> 879 GCells/s), so FP32 loads two
+// planes ahead and FP64, whose three levels of eight cells per lane leave fewer free registers, one.
 template <typename T, int C, int R, int K, int WAVES, bool FMA, bool EDGE, int PF = (sizeof(T) == 4 ? 2 : 1)>
 __device__ __forceinline__ void stream3_run(const Stream3Args& A, const Tile3Desc& d, int zo0, int zo1, T* lds)
 {
