@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <functional>
+#include <queue>
 
 namespace dtb {
 
@@ -592,17 +594,54 @@ bool split_axis3(int64_t n, int E, int K, std::vector<Span3>* out)
     }
 }
 
+// Makespan, in plane iterations, of a streaming launch: its workgroups, dispatched in launch order (z-block by
+// z-block, the tiles of a block in turn) onto n_cu compute units, one at a time on each, each taking one
+// iteration per plane it streams (its z-block and the K-plane rings, clipped to the grid).  Past 32 waves of
+// workgroups the order hardly matters and the even share is taken instead.
+static double stream3_makespan(int64_t depth, int zb, int K, int64_t ntiles, int n_cu)
+{
+    const int64_t nz = (depth + zb - 1) / zb;
+    auto iters = [&](int64_t b) {
+        const int64_t z0 = 1 + b * zb, z1 = std::min<int64_t>(z0 + zb, depth + 1);
+        return (double)(std::min<int64_t>(z1 + K, depth + 2) - std::max<int64_t>(z0 - K, 0));
+    };
+    if (ntiles * nz > 32 * (int64_t)n_cu) {
+        double total = 0, longest = 0;
+        for (int64_t b = 0; b < nz; ++b) {
+            total += iters(b) * (double)ntiles;
+            longest = std::max(longest, iters(b));
+        }
+        return total / n_cu + longest;
+    }
+    std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;  // per compute unit
+    for (int i = 0; i < n_cu; ++i) free_at.push(0.0);
+    double end = 0;
+    for (int64_t b = 0; b < nz; ++b) {
+        const double it = iters(b);
+        for (int64_t t = 0; t < ntiles; ++t) {
+            const double f = free_at.top() + it;
+            free_at.pop();
+            free_at.push(f);
+            end = std::max(end, f);
+        }
+    }
+    return end;
+}
+
 double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int elem_bytes, int64_t depth,
                          int64_t interior_cells, bool* bytes_bound)
 {
     // Measured on MI355X (512^3, one workgroup per compute unit): a launch streams at about 4.3 TB/s (of the
-    // bytes below) when every compute unit holds a workgroup, and each compute unit pulls its share, so fewer
-    // workgroups than compute units, or a last partial wave of them, leave bandwidth unused.  Bytes: every
-    // z-block loads its tile for its planes and a K-deep ring below and above; the owned cells are stored
-    // once.  Compute: a workgroup takes about 130 ps per cell and level for every plane it streams (its
-    // K-plane rings included), whatever the precision (the FP64 and FP32 VALU rates are the same and the
-    // FP32 tile is twice as wide); the workgroups share the compute units.  FP64 (half the cells per plane)
-    // is bound by the bytes, FP32 by the compute, which favours deep z-blocks (fewer ring planes).
+    // bytes below) when every compute unit holds a workgroup, and each compute unit pulls its share, so
+    // fewer workgroups than compute units leave bandwidth unused.  Bytes: every z-block loads its tile for
+    // its planes and a K-deep ring below and above; the owned cells are stored once.  Compute: a workgroup
+    // takes about 130 ps per cell and level for every plane it streams (its rings included), whatever the
+    // precision (the FP64 and FP32 VALU rates are the same and the FP32 tile is twice as wide), one
+    // workgroup per compute unit at a time, so the launch takes the makespan of its workgroups in launch
+    // order (stream3_makespan).  That order decides the tail: the measured 512^3 launches rank as the
+    // makespan does (FP32: one wave of 240 workgroups of 134 planes 905 GCells/s, two of 70 planes 893,
+    // two of 108 756; FP64 with 11 z-blocks of 51 planes, the last one 2 planes short, 729 against 681 with
+    // 12 of 46).  FP64 (half the cells per plane) is bound by the bytes, FP32 by the compute.
     const double bw = 4.3e6;  // bytes per microsecond
     const int64_t nz = (depth + zb - 1) / zb;
     const int64_t tiles = nz > 0 ? nwg / nz : nwg;
@@ -613,9 +652,9 @@ double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int e
     }
     const double bytes = planes * tiles * ER * EC * elem_bytes + (double)interior_cells * elem_bytes;
     const double w = (double)nwg / std::max(1, n_cu);
-    const double mem = bytes / bw * (std::ceil(w) / w);
+    const double mem = bytes / bw / std::min(w, 1.0);
     const double cell = 130e-6;  // microseconds per cell and level
-    const double compute = std::max(w, 1.0) * (zb + 2.0 * K) * ((double)ER * EC * cell * K + 0.3);
+    const double compute = stream3_makespan(depth, zb, K, tiles, n_cu) * ((double)ER * EC * cell * K + 0.3);
     if (bytes_bound) *bytes_bound = mem >= compute;
     return std::max(mem, compute);
 }
@@ -625,10 +664,12 @@ int choose_zblock(int64_t ntiles, int ER, int EC, int K, int elem_bytes, int64_t
 {
     // The block height with the least modelled launch time: taller blocks amortise the K-deep z ring, more
     // blocks fill the compute units.  Measured at 512^3: a launch bound by its memory traffic (FP64) streams
-    // best with several waves of workgroups queued per compute unit (46-48 planes per block, 1100-1200
-    // workgroups, beat 64-128 planes by 1.08-1.09x), so for such launches blocks that leave fewer than four
-    // workgroups per compute unit are taken only when the grid is too shallow for more; a compute-bound one
-    // (FP32) is best with the fewest ring planes (64-128 planes per block beat 18 by 1.12-1.13x).
+    // best with several waves of workgroups queued per compute unit (41-51 planes per block, 1100-1300
+    // workgroups, beat 64-128 planes by 1.1x), so for such launches blocks that leave fewer than four
+    // workgroups per compute unit are taken only when the grid is too shallow for more (among those, 51
+    // planes per block, 729 GCells/s, beat 46, 681: stream3_launch_us); a compute-bound one (FP32) is best
+    // with the fewest ring planes in whole waves of workgroups (128 planes per block, one wave, 905
+    // GCells/s; 64, two waves, 893; 18, seven, 801).
     double best = 1e300;
     int zb = 1;
     const int64_t want = 4 * (int64_t)n_cu;

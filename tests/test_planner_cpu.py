@@ -250,14 +250,15 @@ def test_split3_covers_axis_with_deep_enough_rings(n, E, K):
 
 def test_zblock_choice_matches_the_measured_optima():
     """The z-block heights the 3-D planner picks at 512^3, where the alternatives were timed on an MI355X: FP64
-    (bound by its memory traffic) keeps at least four workgroups per compute unit (46 planes: 12 blocks x 100
-    tiles, best within 2 % of 18-48 planes, 8 % ahead of 64-128); FP32 (compute-bound) takes deep blocks, which
-    minimise the ring planes (64 planes, 12 % ahead of 18)."""
+    (bound by its memory traffic) keeps at least four workgroups per compute unit and, among those, the
+    shortest modelled tail (51 planes: 11 blocks x 100 tiles, the last block 2 planes; 729 GCells/s against 681
+    for 46 and 634-645 for 64-128); FP32 (compute-bound) takes deep blocks in whole waves of workgroups (128
+    planes: one wave of 240 workgroups, 905 against 893 for 64 and 801 for 18)."""
     cells = 512 ** 3
     z64 = dtb.test_zblock(100, 32, 128, 3, 8, 512, cells)
     z32 = dtb.test_zblock(60, 32, 256, 3, 4, 512, cells)
-    assert z64 == 46 and 100 * -(-512 // z64) >= 4 * 256
-    assert z32 == 64
+    assert z64 == 51 and 100 * -(-512 // z64) >= 4 * 256
+    assert z32 == 128
     # Shallow grids: a height within the grid; invalid arguments are refused.
     for depth in (1, 5, 30):
         z = dtb.test_zblock(100, 32, 128, 3, 8, depth, depth * 500 * 500)
