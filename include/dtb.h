@@ -111,6 +111,10 @@ typedef struct {
                             above): step, resident and sweep paths, 8 waves, neighbour flags; register
                             tiles FP64 4 x 8 and FP32 4 x 16 per lane (rows_per_lane 8 / 16); 7: j3d7pt,
                             dtb_plan3d only */
+    int32_t cols_per_lane; /* dtb_plan3d's streaming path only (0 elsewhere): columns per lane of the register
+                              tile, 0 = choose.  Instantiated: FP64 2; FP32 4 and 3 (tiles 256 and 192 columns
+                              wide; "choose" takes the one whose overlapping tiles compute fewer columns,
+                              4 on a tie).  Any other value: DTB_ERR_UNSUPPORTED. */
 } dtb_plan_opts;
 
 /* A 3-D grid in device memory (dtb_plan3d): (depth + 2) planes of plane_pitch elements, each plane
@@ -289,9 +293,9 @@ dtb_status dtb_run_noalloc(const dtb_grid* grid, const double coeffs[5], int64_t
  * of time levels, with a ghost_k-deep ring of redundant cells in every axis
  * and no synchronisation between workgroups -- or DTB_PATH_STEP (one launch per
  * step, HBM to HBM).  Options other than path, ghost_k, depth_D (0 = chosen by
- * the planner), rows_per_lane (0 or the instance's: FP64 2 x 4 and FP32 4 x 4
- * cells per lane and plane), max_wg, exact and stencil (0 or 7) must be 0:
- * DTB_ERR_UNSUPPORTED.  Invalid shapes: DTB_ERR_INVALID_ARG, before any HIP
+ * the planner), rows_per_lane (0 or the instance's: 4), cols_per_lane (0 or an
+ * instance's: FP64 2 x 4, FP32 4 x 4 and 3 x 4 cells per lane and plane),
+ * max_wg, exact and stencil (0 or 7) must be 0: DTB_ERR_UNSUPPORTED.  Invalid shapes: DTB_ERR_INVALID_ARG, before any HIP
  * call.  Allocates; describe() reports big_tiles = z-blocks and stencil = 7.
  */
 dtb_status dtb_plan3d(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t cols, int64_t pitch,

@@ -71,6 +71,14 @@ int32_t dtb_test_split3(int64_t n, int32_t E, int32_t K, int32_t* out, int32_t m
 int32_t dtb_test_zblock(int64_t ntiles, int32_t ext_rows, int32_t ext_cols, int32_t K, int32_t elem_bytes,
                         int64_t depth, int64_t interior_cells, int32_t n_cu);
 
+/*
+ * The columns per lane of the streaming instance the j3d7pt planner
+ * (dtb_plan3d) picks when cols_per_lane is left open, for a grid `cols`
+ * interior columns wide, dtype DTB_F64 or DTB_F32 and K steps per launch
+ * (1 .. 3).  Returns -1 if an argument is invalid.  Host only.
+ */
+int32_t dtb_test_cols3(int32_t dtype, int64_t cols, int32_t K);
+
 #define DTB_TEST_BATCH_STRIDE 13
 
 /*

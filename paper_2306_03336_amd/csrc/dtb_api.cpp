@@ -120,7 +120,8 @@ dtb_status check_opts(const dtb_plan_opts* o)
     if (o->path < DTB_PATH_AUTO || o->path > DTB_PATH_STREAM3D) return DTB_ERR_INVALID_ARG;
     if (o->sync != 0 && o->sync != 1) return DTB_ERR_INVALID_ARG;
     if (o->stencil != 0 && o->stencil != 5 && o->stencil != 7 && o->stencil != 9) return DTB_ERR_INVALID_ARG;
-    if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0) return DTB_ERR_INVALID_ARG;
+    if (o->ghost_k < 0 || o->depth_D < 0 || o->rows_per_lane < 0 || o->max_wg < 0 || o->cols_per_lane < 0)
+        return DTB_ERR_INVALID_ARG;
     if (o->waves != 0 && o->waves != 4 && o->waves != 8) return DTB_ERR_INVALID_ARG;
     if (o->exact != 0 && o->exact != 1) return DTB_ERR_INVALID_ARG;
     if ((o->debug_flags & ~(DTB_DEBUG_TINY_SPIN | DTB_DEBUG_POISON | DTB_DEBUG_TIMING | DTB_DEBUG_DIRECT_XCHG)) != 0 ||
@@ -138,6 +139,7 @@ int stencil_points(const dtb_plan_opts& o) { return o.stencil == 9 ? 9 : 5; }
 dtb_status check_instance(const dtb_plan_opts& o, int dtype)
 {
     if (o.stencil == 7 || o.path == DTB_PATH_STREAM3D) return DTB_ERR_UNSUPPORTED;  // 3-D: dtb_plan3d
+    if (o.cols_per_lane != 0) return DTB_ERR_UNSUPPORTED;  // the 2-D instances are chosen by rows_per_lane
     const int pts = stencil_points(o);
     if (pts == 9 && (o.path == DTB_PATH_OVERLAPPED || o.waves == 4 || o.sync == 1)) return DTB_ERR_UNSUPPORTED;
     if (o.path == DTB_PATH_STEP) return DTB_OK;
@@ -1098,6 +1100,25 @@ dtb_status check_shape3(int64_t depth, int64_t rows, int64_t cols, int64_t pitch
     return DTB_OK;
 }
 
+// Columns per lane of the streaming instance for a grid `cols` wide: the one whose overlapping column tiles
+// (split_axis3) compute the fewest columns, the wider on a tie.  FP64 has one instance.
+int stream3_cols_per_lane(int dtype, int64_t cols, int K)
+{
+    if (dtype != DTB_F32) return 2;
+    int best = 4;
+    int64_t best_cols = INT64_MAX;
+    for (int c : {4, 3}) {
+        std::vector<Span3> xs;
+        if (!split_axis3(cols, kWaveSize * c, K, &xs)) continue;
+        const int64_t computed = (int64_t)xs.size() * kWaveSize * c;
+        if (computed < best_cols) {
+            best_cols = computed;
+            best = c;
+        }
+    }
+    return best;
+}
+
 dtb_status plan3d_impl(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t cols, int64_t pitch,
                        int64_t plane_pitch, int dtype, const dtb_plan_opts* opts)
 {
@@ -1120,8 +1141,11 @@ dtb_status plan3d_impl(dtb_plan_t* out, int64_t depth, int64_t rows, int64_t col
     int C = 0, R = 0;
     const int K = o.ghost_k > 0 ? o.ghost_k : 3;
     if (path == DTB_PATH_STREAM3D) {
-        if (!dtb_stream3d_kernel(dtype, K, fma, &C, &R)) return DTB_ERR_UNSUPPORTED;
+        const int want = o.cols_per_lane > 0 ? o.cols_per_lane : stream3_cols_per_lane(dtype, cols, K);
+        if (!dtb_stream3d_kernel(dtype, K, fma, want, &C, &R)) return DTB_ERR_UNSUPPORTED;
         if (o.rows_per_lane != 0 && o.rows_per_lane != R) return DTB_ERR_UNSUPPORTED;
+    } else if (o.cols_per_lane != 0) {
+        return DTB_ERR_UNSUPPORTED;
     }
     DeviceInfo di;
     if (!device_info(&di)) return DTB_ERR_HIP;
@@ -1220,7 +1244,7 @@ dtb_status run3d_impl(dtb_plan_t p, const dtb_grid3d* g, const double* coeffs, i
             // The last launch may take fewer steps: the K-step layout serves it (a deeper ring than needed).
             const int k = (int)std::min<int64_t>(p->K3, T - done);
             int C = 0, R = 0;
-            const void* f = dtb_stream3d_kernel(p->dtype, k, p->fma, &C, &R);
+            const void* f = dtb_stream3d_kernel(p->dtype, k, p->fma, p->C3, &C, &R);
             if (!f) return DTB_ERR_UNSUPPORTED;
             A.src = bufs[rounds & 1];
             A.dst = bufs[(rounds + 1) & 1];
@@ -1547,6 +1571,12 @@ int32_t dtb_test_zblock(int64_t ntiles, int32_t ext_rows, int32_t ext_cols, int3
         interior_cells < 1 || n_cu < 1)
         return -1;
     return choose_zblock(ntiles, ext_rows, ext_cols, K, elem_bytes, depth, interior_cells, n_cu);
+}
+
+int32_t dtb_test_cols3(int32_t dtype, int64_t cols, int32_t K)
+{
+    if ((dtype != DTB_F64 && dtype != DTB_F32) || cols < 1 || K < 1 || K > 3) return -1;
+    return stream3_cols_per_lane(dtype, cols, K);
 }
 
 }  // extern "C"

@@ -1,5 +1,5 @@
-// dtb_inst_3d.hip -- the j3d7pt kernels: the streaming kernels (FP64 2 x 4 and FP32 4 x 4 cells per lane and
-// plane, 8 waves, K = 1, 2, 3 steps per launch, fused and exact arithmetic), the one-step baseline and the
+// dtb_inst_3d.hip -- the j3d7pt kernels: the streaming kernels (FP64 2 x 4, FP32 4 x 4 and 3 x 4 cells per lane
+// and plane, 8 waves, K = 1, 2, 3 steps per launch, fused and exact arithmetic), the one-step baseline and the
 // copies around them, with their host-side launchers.
 #include "dtb_stream3d.h"
 
@@ -12,12 +12,15 @@ static const void* stream_pick(bool fma)
                : (const void*)&k_stream3d<T, C, R, K, kStreamWaves, false>;
 }
 
-// The streaming kernel for (dtype, steps per launch K), or nullptr; *C, *R: the instance's cells per lane.
-const void* dtb_stream3d_kernel(int dtype, int K, bool fma, int* C, int* R)
+// The streaming kernel for (dtype, steps per launch K, columns per lane: 0 = the default instance), or nullptr;
+// *C, *R: the instance's cells per lane.  FP64 2 x 4; FP32 4 x 4 (the default) and 3 x 4 (its 192-column tiles
+// cover some widths with fewer ring columns: 512 columns in three spans of 192 instead of three of 256).
+const void* dtb_stream3d_kernel(int dtype, int K, bool fma, int cols_per_lane, int* C, int* R)
 {
+    *R = 4;
     if (dtype == 0) {
         *C = 2;
-        *R = 4;
+        if (cols_per_lane != 0 && cols_per_lane != 2) return nullptr;
         switch (K) {
         case 1: return stream_pick<double, 2, 4, 1>(fma);
         case 2: return stream_pick<double, 2, 4, 2>(fma);
@@ -25,8 +28,17 @@ const void* dtb_stream3d_kernel(int dtype, int K, bool fma, int* C, int* R)
         default: return nullptr;
         }
     }
+    if (cols_per_lane == 3) {
+        *C = 3;
+        switch (K) {
+        case 1: return stream_pick<float, 3, 4, 1>(fma);
+        case 2: return stream_pick<float, 3, 4, 2>(fma);
+        case 3: return stream_pick<float, 3, 4, 3>(fma);
+        default: return nullptr;
+        }
+    }
     *C = 4;
-    *R = 4;
+    if (cols_per_lane != 0 && cols_per_lane != 4) return nullptr;
     switch (K) {
     case 1: return stream_pick<float, 4, 4, 1>(fma);
     case 2: return stream_pick<float, 4, 4, 2>(fma);

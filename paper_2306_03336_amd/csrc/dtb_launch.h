@@ -48,8 +48,9 @@ const void* dtb_ovl_kernel(int dtype, int R, bool fma, bool colmask, bool rowche
 // ---- j3d7pt (dtb_inst_3d.hip)
 
 // The K-step streaming kernel (arguments: Stream3Args, Tile3Desc table) for
-// dtype and K (1 .. 3), or nullptr; *C, *R: columns and rows per lane.
-const void* dtb_stream3d_kernel(int dtype, int K, bool fma, int* C, int* R);
+// dtype, K (1 .. 3) and columns per lane (0: the default instance), or
+// nullptr; *C, *R: columns and rows per lane.
+const void* dtb_stream3d_kernel(int dtype, int K, bool fma, int cols_per_lane, int* C, int* R);
 // One step of the untiled baseline (seven coefficients c, n, s, e, w, t, b).
 hipError_t launch_step3d(int dtype, bool fma, const void* in, void* out, int64_t pitch, int64_t plane_pitch,
                          int depth, int rows, int cols, const double* coeffs, hipStream_t st);

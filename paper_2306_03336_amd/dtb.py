@@ -53,7 +53,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("ghost_k", ctypes.c_int32), ("depth_D", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("max_wg", ctypes.c_int32), ("exact", ctypes.c_int32),
                 ("debug_flags", ctypes.c_int32), ("tune", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("sync", ctypes.c_int32), ("stencil", ctypes.c_int32)]
+                ("sync", ctypes.c_int32), ("stencil", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -65,7 +65,7 @@ class Problem(ctypes.Structure):
 EXPORTS = ("dtb_plan", "dtb_run_plan", "dtb_run", "dtb_run_batched", "dtb_plan_check", "dtb_plan_describe",
            "dtb_plan_destroy", "dtb_cache_clear", "dtb_status_string", "dtb_test_layout", "dtb_test_sweep",
            "dtb_batch_check", "dtb_test_batch", "dtb_plan_timing", "dtb_probe", "dtb_run_noalloc", "dtb_plan3d",
-           "dtb_run3d_plan", "dtb_test_split3", "dtb_test_zblock")
+           "dtb_run3d_plan", "dtb_test_split3", "dtb_test_zblock", "dtb_test_cols3")
 TEST_SWEEP_STRIDE = 17 + TEST_MAX_NEIGHBOURS
 
 _lib = None
@@ -96,6 +96,8 @@ def load():
     lib.dtb_test_zblock.restype = ctypes.c_int32
     lib.dtb_test_zblock.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
+    lib.dtb_test_cols3.restype = ctypes.c_int32
+    lib.dtb_test_cols3.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
     lib.dtb_run.restype = ctypes.c_int
     lib.dtb_run.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int, P]
     lib.dtb_run_batched.restype = ctypes.c_int
@@ -257,10 +259,11 @@ class Plan3D(Plan):
 
     def __init__(self, depth: int, rows: int, cols: int, pitch: int, plane_pitch: int, dtype: int,
                  path: int = PATH_AUTO, ghost_k: int = 0, depth_D: int = 0, rows_per_lane: int = 0, max_wg: int = 0,
-                 exact: bool = False):
+                 exact: bool = False, cols_per_lane: int = 0):
         lib = load()
         self._h = ctypes.c_void_p()
-        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, 0, 0, 0, 0, 7)
+        opts = PlanOpts(path, ghost_k, depth_D, rows_per_lane, max_wg, 1 if exact else 0, 0, 0, 0, 0, 7,
+                        cols_per_lane)
         _check(lib.dtb_plan3d(ctypes.byref(self._h), depth, rows, cols, pitch, plane_pitch, dtype, ctypes.byref(opts)),
                "dtb_plan3d")
         self.rows, self.cols, self.pitch, self.dtype = rows, cols, pitch, dtype
@@ -364,6 +367,12 @@ def test_zblock(ntiles: int, ext_rows: int, ext_cols: int, K: int, elem_bytes: i
     """The z-block height the 3-D streaming planner picks, without a GPU (or None for invalid arguments)."""
     z = load().dtb_test_zblock(ntiles, ext_rows, ext_cols, K, elem_bytes, depth, interior_cells, n_cu)
     return None if z < 0 else z
+
+
+def test_cols3(dtype: int, cols: int, K: int = 3):
+    """The columns per lane of the 3-D streaming instance the planner picks, without a GPU (None: invalid)."""
+    c = load().dtb_test_cols3(dtype, cols, K)
+    return None if c < 0 else c
 
 
 def test_sweep(rows: int, cols: int, rows_per_lane: int, cols_per_lane: int, waves: int, k: int, D: int,

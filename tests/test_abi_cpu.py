@@ -175,9 +175,18 @@ def test_plan3d_rejects_bad_shapes_and_options_before_any_hip_call():
     for fields in (dict(path=dtb.PATH_RESIDENT), dict(path=dtb.PATH_SWEEP), dict(ghost_k=4), dict(sync=1),
                    dict(tune=1), dict(waves=4), dict(debug_flags=dtb.DEBUG_POISON)):
         assert rc(4, 4, 4, 6, 36, **fields) == -2, fields
-    # and a 2-D plan refuses the 3-D stencil and path
+    # columns per lane: an instance's (FP64 2; FP32 4 or 3), else unsupported; negative: invalid
+    assert rc(4, 4, 4, 6, 36, cols_per_lane=-1) == -1
+    for dtype, fields in ((dtb.F64, dict(cols_per_lane=3)), (dtb.F64, dict(cols_per_lane=4)),
+                          (dtb.F32, dict(cols_per_lane=2)), (dtb.F32, dict(cols_per_lane=5)),
+                          (dtb.F32, dict(cols_per_lane=3, rows_per_lane=8)),
+                          (dtb.F64, dict(cols_per_lane=2, path=dtb.PATH_STEP))):
+        assert rc(4, 4, 4, 6, 36, dtype=dtype, **fields) == -2, (dtype, fields)
+    # and a 2-D plan refuses the 3-D stencil and path, and the 3-D column choice
     assert _plan_rc(64, 64, 66, 0, _opts(stencil=7)) == -2
     assert _plan_rc(64, 64, 66, 0, _opts(path=dtb.PATH_STREAM3D)) == -2
+    assert _plan_rc(64, 64, 66, 0, _opts(cols_per_lane=2)) == -2
+    assert _plan_rc(64, 64, 66, 0, _opts(cols_per_lane=-2)) == -1
 
 
 def _opts(**fields):

@@ -59,9 +59,13 @@ def _run(u, coeffs, T, dtype=np.float64, cols=None, **opts):
 SHAPES = [(1, 1, 1), (3, 5, 7), (9, 40, 130), (17, 33, 300), (40, 70, 129), (5, 200, 90), (30, 64, 256)]
 
 
+# (precision, columns per lane): every streaming instance.
+INSTANCES = [("f64", 2), ("f32", 4), ("f32", 3)]
+
+
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_3d_stream_exact_bitwise(shape, dtype):
+@pytest.mark.parametrize("dtype,cpl", INSTANCES, ids=lambda v: str(v))
+def test_3d_stream_exact_bitwise(shape, dtype, cpl):
     depth, rows, cols = shape
     npd = np.float64 if dtype == "f64" else np.float32
     ref_fn = oracle.j3d7pt_f64 if dtype == "f64" else oracle.j3d7pt_f32
@@ -69,16 +73,18 @@ def test_3d_stream_exact_bitwise(shape, dtype):
     coeffs = inputs.weights7(rng)
     u = _random_shell(inputs.uniform_grid3(depth, rows, cols, rng), rng).astype(npd)
     for K, T, zb in [(3, 7, 0), (3, 3, 4), (2, 5, 3), (1, 4, 0), (3, 10, 5), (2, 1, 0)]:
-        _say("3d exact", dtype, shape, "K", K, "T", T, "zb", zb)
-        got, desc = _run(u, coeffs, T, dtype=npd, path=dtb.PATH_STREAM3D, ghost_k=K, depth_D=zb, exact=True)
+        _say("3d exact", dtype, "cols/lane", cpl, shape, "K", K, "T", T, "zb", zb)
+        got, desc = _run(u, coeffs, T, dtype=npd, path=dtb.PATH_STREAM3D, ghost_k=K, depth_D=zb, exact=True,
+                         cols_per_lane=cpl)
         assert desc["path"] == dtb.PATH_STREAM3D and desc["stencil"] == 7 and desc["ghost_k"] == K, desc
+        assert desc["cols_per_lane"] == cpl, desc
         ref = ref_fn(u, coeffs, T)
         assert np.array_equal(got, ref), (shape, K, T, zb, float(np.max(np.abs(got.astype(float) - ref))))
 
 
 @pytest.mark.parametrize("shape", [(64, 40, 130), (50, 33, 300)], ids=lambda s: "x".join(map(str, s)))
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_3d_stream_exact_bitwise_deep_blocks(shape, dtype):
+@pytest.mark.parametrize("dtype,cpl", INSTANCES, ids=lambda v: str(v))
+def test_3d_stream_exact_bitwise_deep_blocks(shape, dtype, cpl):
     """Deep z-blocks, so that most iterations of a workgroup run the streaming loop's branch-free steady state
     (every plane loaded ahead, every level producing an interior plane); shallow ones and the ends of the grid
     take the general form.  Both must equal the oracle bit for bit."""
@@ -89,9 +95,11 @@ def test_3d_stream_exact_bitwise_deep_blocks(shape, dtype):
     coeffs = inputs.weights7(rng)
     u = _random_shell(inputs.uniform_grid3(depth, rows, cols, rng), rng).astype(npd)
     for K, T, zb in [(3, 7, depth), (3, 4, 30), (2, 5, 25), (1, 3, depth), (3, 9, 17)]:
-        _say("3d exact deep", dtype, shape, "K", K, "T", T, "zb", zb)
-        got, desc = _run(u, coeffs, T, dtype=npd, path=dtb.PATH_STREAM3D, ghost_k=K, depth_D=zb, exact=True)
+        _say("3d exact deep", dtype, "cols/lane", cpl, shape, "K", K, "T", T, "zb", zb)
+        got, desc = _run(u, coeffs, T, dtype=npd, path=dtb.PATH_STREAM3D, ghost_k=K, depth_D=zb, exact=True,
+                         cols_per_lane=cpl)
         assert desc["path"] == dtb.PATH_STREAM3D and desc["ghost_k"] == K and desc["depth_D"] == zb, desc
+        assert desc["cols_per_lane"] == cpl, desc
         ref = ref_fn(u, coeffs, T)
         assert np.array_equal(got, ref), (shape, K, T, zb, float(np.max(np.abs(got.astype(float) - ref))))
 
@@ -151,6 +159,23 @@ def test_3d_fma_within_tolerance_and_tiling_invariant():
     assert _err3(a, oracle.j3d7pt_f64(u, coeffs, T), cols) <= TOL_F64
     for K, zb in [(1, 0), (2, 7), (3, 3)]:
         b, _ = _run(u, coeffs, T, ghost_k=K, depth_D=zb)
+        assert np.array_equal(a, b), (K, zb)
+
+
+def test_3d_f32_instances_agree_bitwise_in_fused_mode():
+    """The two FP32 streaming instances (4 and 3 columns per lane) compute each cell with the same fused chain
+    in the same order, so the default mode gives the same bits whichever covers the grid; at 372 columns the
+    planner takes 3 (two spans of 192 against two of 256)."""
+    depth, rows, cols, T = 30, 64, 372, 11
+    rng = np.random.default_rng(8)
+    coeffs = inputs.weights7(rng)
+    u = _random_shell(inputs.uniform_grid3(depth, rows, cols, rng), rng).astype(np.float32)
+    _say("3d f32 instances", depth, rows, cols, T)
+    a, d = _run(u, coeffs, T, dtype=np.float32)
+    assert d["cols_per_lane"] == 3 and d["exact"] == 0, d
+    for K, zb in [(3, 0), (2, 9), (1, 0)]:
+        b, db = _run(u, coeffs, T, dtype=np.float32, ghost_k=K, depth_D=zb, cols_per_lane=4)
+        assert db["cols_per_lane"] == 4, db
         assert np.array_equal(a, b), (K, zb)
 
 

@@ -253,18 +253,46 @@ def test_zblock_choice_matches_the_measured_optima():
     (bound by its memory traffic) keeps at least four workgroups per compute unit and, among those, the
     shortest modelled tail (51 planes: 11 blocks x 100 tiles, the last block 2 planes; 729 GCells/s against 681
     for 46 and 634-645 for 64-128); FP32 (compute-bound) takes deep blocks in whole waves of workgroups (128
-    planes: one wave of 240 workgroups, 905 against 893 for 64 and 801 for 18)."""
+    planes: one wave of 240 workgroups; with 4 columns per lane 905 against 893 for 64 and 801 for 18, with 3
+    columns per lane, the instance the planner takes at this width, 1180 against 1181 for 64 and 951-988 for
+    86-171)."""
     cells = 512 ** 3
     z64 = dtb.test_zblock(100, 32, 128, 3, 8, 512, cells)
     z32 = dtb.test_zblock(60, 32, 256, 3, 4, 512, cells)
+    z32c3 = dtb.test_zblock(60, 32, 192, 3, 4, 512, cells)
     assert z64 == 51 and 100 * -(-512 // z64) >= 4 * 256
-    assert z32 == 128
+    assert z32 == 128 and z32c3 == 128
     # Shallow grids: a height within the grid; invalid arguments are refused.
     for depth in (1, 5, 30):
         z = dtb.test_zblock(100, 32, 128, 3, 8, depth, depth * 500 * 500)
         assert 1 <= z <= depth
     assert dtb.test_zblock(0, 32, 128, 3, 8, 512, cells) is None
     assert dtb.test_zblock(100, 32, 128, 3, 2, 512, cells) is None
+
+
+def test_cols3_choice_takes_the_fewest_computed_columns():
+    """FP32 has two streaming instances, 4 and 3 columns per lane (tiles 256 and 192 wide, K-deep rings on
+    both sides); the planner takes the one whose overlapping spans compute fewer columns, 4 on a tie.  512
+    columns: three spans of 256 (768 computed) against three of 192 (576): 3 (measured at 512^3, K = 3: 1180
+    against 904 GCells/s, the same output bit for bit).  1000 columns: four of 256 (1024) against six of 192
+    (1152): 4.  FP64 has one instance, 2."""
+    def computed(n, c, K):
+        return len(dtb.test_split3(n, 64 * c, K)) * 64 * c
+
+    assert dtb.test_cols3(dtb.F32, 512, 3) == 3
+    assert dtb.test_cols3(dtb.F32, 1000, 3) == 4
+    assert dtb.test_cols3(dtb.F32, 250, 3) == 4     # one span of 256 against two of 192
+    assert dtb.test_cols3(dtb.F32, 186, 3) == 3     # one span of each: 192 computed against 256
+    for n in (1, 7, 100, 186, 187, 250, 251, 500, 512, 700, 1000, 1500, 4096):
+        for K in (1, 2, 3):
+            c = dtb.test_cols3(dtb.F32, n, K)
+            assert computed(n, c, K) == min(computed(n, 4, K), computed(n, 3, K)), (n, K)
+            if computed(n, 4, K) == computed(n, 3, K):
+                assert c == 4, (n, K)
+            assert dtb.test_cols3(dtb.F64, n, K) == 2
+    assert dtb.test_cols3(dtb.F32, 0, 3) is None
+    assert dtb.test_cols3(dtb.F32, 512, 4) is None
+    assert dtb.test_cols3(2, 512, 3) is None
 
 
 def test_split3_refuses_short_ranges():
