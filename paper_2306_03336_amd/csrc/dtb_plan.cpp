@@ -639,9 +639,10 @@ double stream3_launch_us(int nwg, int n_cu, int ER, int EC, int zb, int K, int e
     // precision (the FP64 and FP32 VALU rates are the same and the FP32 tile is twice as wide), one
     // workgroup per compute unit at a time, so the launch takes the makespan of its workgroups in launch
     // order (stream3_makespan).  That order decides the tail: the measured 512^3 launches rank as the
-    // makespan does (FP32: one wave of 240 workgroups of 134 planes 905 GCells/s, two of 70 planes 893,
-    // two of 108 756; FP64 with 11 z-blocks of 51 planes, the last one 2 planes short, 729 against 681 with
-    // 12 of 46).  FP64 (half the cells per plane) is bound by the bytes, FP32 by the compute.
+    // makespan does (FP32 with 4 columns per lane: one wave of 240 workgroups of 134 planes 905 GCells/s,
+    // two of 70 planes 893, two of 108 756; with 3 columns per lane the same order, 1180, 1180 and 951-988;
+    // FP64 with 11 z-blocks of 51 planes, the last one 2 planes short, 729 against 681 with 12 of 46).
+    // FP64 (half the cells per plane) is bound by the bytes, FP32 by the compute.
     const double bw = 4.3e6;  // bytes per microsecond
     const int64_t nz = (depth + zb - 1) / zb;
     const int64_t tiles = nz > 0 ? nwg / nz : nwg;
@@ -669,7 +670,9 @@ int choose_zblock(int64_t ntiles, int ER, int EC, int K, int elem_bytes, int64_t
     // workgroups per compute unit are taken only when the grid is too shallow for more (among those, 51
     // planes per block, 729 GCells/s, beat 46, 681: stream3_launch_us); a compute-bound one (FP32) is best
     // with the fewest ring planes in whole waves of workgroups (128 planes per block, one wave, 905
-    // GCells/s; 64, two waves, 893; 18, seven, 801).
+    // GCells/s; 64, two waves, 893; 18, seven, 801; with 3 columns per lane 128 and 64 both 1180).  FP64
+    // blocks of 103 planes (two waves of 500 workgroups) measured 1-3 % above 51 on three boxes; the
+    // bytes model does not see the difference, and the rule above keeps 51.
     double best = 1e300;
     int zb = 1;
     const int64_t want = 4 * (int64_t)n_cu;
