@@ -170,9 +170,11 @@ int64_t spill_bytes(const void* f)
 bool spills(const void* f) { return spill_bytes(f) != 0; }
 
 // The sweep may take a kernel that spills a few words (in the sweep kernels
-// these are tile-loop values, reloaded once per big tile): measured at
-// 16384^2 FP32, 24 rows per lane with 16 bytes of spill beat the 16-row tile
-// by 6 %.  Its modelled time carries a 10 % penalty per such kernel.
+// these are tile-loop values, reloaded once per big tile), priced like any
+// other: measured at 16384^2 FP32, 24 rows per lane with 16 bytes of spill
+// beat the 16-row tile by 6 %, and at 3072^2 FP64 24 rows per lane (12 bytes)
+// beat the 16-row tile by 13 % (1572 against 1385 GCells/s), an order that a
+// 10 % penalty on spilling kernels used to reverse.
 constexpr int64_t kSweepSpillSlack = 32;
 
 // Choose (rows per lane, k) for the resident path by the static cost model.
@@ -323,7 +325,6 @@ bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o,
         const void* f = dtb_sweep_kernel(dtype, R, fma, cm, rc, &C, &waves, pts);
         const int64_t sb = spill_bytes(f);
         if (sb < 0 || sb > kSweepSpillSlack) continue;
-        const double penalty = sb > 0 ? 1.1 : 1.0;
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, waves * kWaveSize, 0) != hipSuccess) continue;
         int cap = std::min(occ, 1) * n_cu;  // one tile per compute unit: the tiles of a big tile run side by side
@@ -333,7 +334,7 @@ bool choose_sweep(int64_t rows, int64_t cols, int dtype, const dtb_plan_opts& o,
             for (int D : Ds) {
                 SweepPlan sp;
                 if (!plan_sweep(rows, cols, R, C, waves, k, D, cap, kNumXcd, &sp)) continue;
-                const double t = sweep_step_us(sp, dtype, pts) * penalty;
+                const double t = sweep_step_us(sp, dtype, pts);
                 if (t < best_t) {
                     best_t = t;
                     *best = std::move(sp);
